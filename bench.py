@@ -1,0 +1,132 @@
+"""Benchmark: one CC global step of the 16384-body Salpeter Plummer workload.
+
+`python bench.py [--steps K] [--warmup W] [--precision fp64|mixed]` runs W
+untimed and K timed steps on one GPU and prints one JSON line.  A step is one
+global step evolve_cc(all, dt=1/64) (split, recursion into every component,
+drift/kick/drift), started each time from the same initial conditions, which
+are already resident in HBM.  `value` is algorithmic pair interactions per
+second: the pair time steps the splits need (n-1 for a fully connected set,
+n(n-1)/2 otherwise) plus the pairs kicked, divided by the wall time per step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+FLOP_TAU = 48      # FP64 operations of one pair time step, eq. 19 (div and sqrt counted as 1)
+FLOP_KICK = 26     # FP64 operations of one symmetric pair kick, eqs. 8-9
+PEAK_FP64_VECTOR = 78.6e12   # MI355X: 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
+
+
+def cpu_baseline(p, dt, eta):
+    """The FP64 oracle on a bounded sample: the top-level split and the
+    top-level kick of the same workload (single host thread)."""
+    import oracle
+    q = p.copy()
+    par = oracle.Params(eta=eta)
+    t0 = time.perf_counter()
+    lab, nt, evals = oracle.split_labels(q, dt, par)
+    pairs = oracle.kick(q, dt, label=lab.astype(np.int64), p=par)
+    t1 = time.perf_counter()
+    return {"value": (evals + pairs) / (t1 - t0), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+            "sample": f"top-level split (BFS, {evals} tau evaluations) and top-level masked kick "
+                      f"({pairs} pairs) of the same 16384-body state, {t1 - t0:.2f} s on one host thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--small-max", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-roofline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
+              "sweep would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import synth
+    from paper_1407_7105_amd import CC_FP64, CC_MIXED, Context, State
+
+    wl = synth.WORKLOADS[2]
+    dt, eta = wl["dt"], wl["eta"]
+    p = synth.workload(2)
+    dev = torch.device("cuda:0")
+    ic = State.from_numpy(p, device=dev)
+    s = ic.copy()
+    prec = CC_FP64 if args.precision == "fp64" else CC_MIXED
+    ctx = Context(device=0, eta=eta, eps2=wl["eps2"], precision=prec, small_max=args.small_max)
+
+    def step():
+        for f in State.FIELDS:
+            getattr(s, f).copy_(getattr(ic, f))
+        return ctx.evolve(s, dt, dt)
+
+    for i in range(args.warmup):
+        t = time.perf_counter()
+        step()
+        print(f"# warmup step {i}: {time.perf_counter() - t:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    work = 0
+    t0 = time.perf_counter()
+    stats = None
+    for _ in range(args.steps):
+        stats = step()
+        work += stats["tau_pairs_alg"] + stats["kick_pairs"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    print(f"# timed: {args.steps} steps, {ms:.2f} ms/step", file=sys.stderr, flush=True)
+    value = work / (t1 - t0)
+
+    roof = None
+    fam = None
+    if not args.no_roofline:
+        # same steps again with every launch bracketed by HIP events on the library's stream
+        ctx.timing(True)
+        for _ in range(args.steps):
+            step()
+        fam = ctx.timing_report()
+        ctx.timing(False)
+        busy = {k: v for k, v in fam.items() if v["launches"]}
+        dom = max(busy, key=lambda k: busy[k]["ms"])
+        d = busy[dom]
+        flops = FLOP_TAU * d["tau_pairs"] + FLOP_KICK * d["kick_pairs"]
+        achieved = flops / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR / 1e12,
+                "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64_VECTOR / 1e12), "traffic": None,
+                "avg_launch_ms": d["ms"] / d["launches"], "launches_per_step": d["launches"] / args.steps}
+
+    out = {
+        "metric": "pair interactions/s", "value": value, "unit": "pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == CC_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "plummer16k_salpeter", "n": p.n, "imf": "salpeter 0.1-100",
+                   "eta": eta, "eps": 0.0, "dt": dt, "step": "one CC global step"},
+        "wall_s_per_nbody_time": (ms / 1e3) / dt,
+        "stats_per_step": stats,
+        "roofline": roof,
+        "kernel_ms_per_step": None if fam is None else
+        {k: round(v["ms"] / args.steps, 4) for k, v in fam.items() if v["launches"]},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, dt, eta)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,182 @@
+/*
+ * cc.h -- C ABI of the MI355X (gfx950) connected-component (CC) N-body
+ * integrator library, after Janes, Pelupessy & Portegies Zwart,
+ * "A connected component-based method for efficiently integrating multiscale
+ * N-body systems" (arXiv:1407.7105).
+ *
+ * Conventions for every entry point:
+ *   - State is structure-of-arrays FP64 in DEVICE memory owned by the caller:
+ *     positions x,y,z, velocities vx,vy,vz and masses m (m > 0), n particles,
+ *     indexed 0..n-1 (the "particle index").  The library never frees or keeps
+ *     caller memory.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     work on it; calls documented as "syncs" wait for their own work before
+ *     returning.  Calls never synchronise the device as a whole.
+ *   - Return value: CC_OK (0) or a negative cc_status.  The message of the last
+ *     failing call on a context is cc_last_error(ctx).  Arguments are checked on
+ *     the host before any launch; a rejected call leaves the state untouched.
+ *   - A context belongs to one device and one host thread at a time; calls on
+ *     one context must not overlap.  Different contexts are independent.
+ *   - Floating-point: every FP64 operation of the plain path is a single
+ *     correctly rounded IEEE-754 operation in the order the paper's formulas
+ *     are written (no contraction), so partitions, kicks and whole steps are
+ *     reproducible run to run and match an FP64 reference that uses the same
+ *     order bit for bit.
+ */
+#ifndef CC_MI355X_H
+#define CC_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CC_OK = 0,
+    CC_ERR_ARG = -1,        /* bad size, pointer, parameter, dt, t_end/dt not a positive integer, mass <= 0 */
+    CC_ERR_NONFINITE = -2,  /* NaN/Inf in the state, or r^2 + eps^2 == 0 in a kick */
+    CC_ERR_DEPTH = -3,      /* recursion deeper than params.max_depth */
+    CC_ERR_DEVICE = -4,     /* HIP runtime error; see cc_last_error */
+    CC_ERR_OOM = -5         /* device or pinned-host allocation failed */
+} cc_status;
+
+typedef enum {
+    CC_FP64 = 0,            /* plain path: every sweep in FP64 */
+    CC_MIXED = 1            /* FP32 sweeps on offsets from the component centre, FP64
+                               state, drift, close pairs and connectivity decisions */
+} cc_precision;
+
+typedef enum {
+    CC_ORDER_FAST = 0,      /* kick sums split over parallel tiles and combined in a
+                               fixed order: deterministic run to run, equal to the
+                               sequential sum up to rounding */
+    CC_ORDER_EXACT = 1      /* every particle sums its partners sequentially in
+                               ascending particle index: bit-identical to a plain
+                               sequential FP64 evaluation of the same formulas */
+} cc_kick_order;
+
+typedef struct cc_ctx cc_ctx;
+
+typedef struct {
+    double *x, *y, *z;      /* positions q_i (device) */
+    double *vx, *vy, *vz;   /* velocities v_i = p_i / m_i (device) */
+    const double *m;        /* masses m_i > 0 (device, read-only) */
+} cc_state;
+
+typedef struct {
+    double eta;             /* time-step accuracy parameter of eq. 19 (> 0, <= 1) */
+    double eps2;            /* Plummer softening squared of eq. 3 (>= 0) */
+    double G;               /* gravitational constant (> 0; 1 in N-body units) */
+    int32_t max_depth;      /* recursion cap (levels below the global step), >= 0 */
+    int32_t precision;      /* cc_precision */
+    int32_t small_max;      /* largest component integrated on chip by one
+                               workgroup (3..1024; 0 = library default) */
+    int32_t kick_order;     /* cc_kick_order */
+} cc_params;
+
+typedef struct {
+    uint64_t tau_pairs;     /* pair time steps evaluated (all launches) */
+    uint64_t tau_pairs_alg; /* pair time steps the split needs: n-1 per fully
+                               connected set, n(n-1)/2 otherwise (Sec. 2.3) */
+    uint64_t kick_pairs;    /* unordered pairs kicked (label_i != label_j) */
+    uint64_t drifts;        /* single-particle half-step drifts */
+    uint64_t components;    /* non-trivial components produced by all splits */
+    uint64_t splits;        /* calls of the split (evolve_cc invocations) */
+    int64_t max_depth_seen; /* deepest recursion level (global step = 0) */
+    double t_reached;       /* integration time completed without error */
+} cc_stats;
+
+/* Create a context on HIP device `hip_device` with parameters *p (copied).
+ * Scratch memory is allocated on demand and kept for reuse. */
+int cc_create(cc_ctx **out, int32_t hip_device, const cc_params *p);
+
+/* Release a context and all its device memory.  NULL is a no-op. */
+void cc_destroy(cc_ctx *ctx);
+
+/* Replace the parameters of a context (same validation as cc_create). */
+int cc_set_params(cc_ctx *ctx, const cc_params *p);
+
+/* Message for the last failing call on ctx ("" if none).  Owned by ctx. */
+const char *cc_last_error(const cc_ctx *ctx);
+
+/* Pair time step tau(i,j) of eq. 19 (Sec. 2.2):
+ *   tau = min( eta t_ff / (1 - eta t_ff'/2), eta t_fb / (1 - eta t_fb'/2) )
+ * with r^2 = |q_i - q_j|^2 + eps^2, mu = G (m_i + m_j), t_ff = sqrt(r^3/mu),
+ * t_ff' = (3/2) t_ff (q.u)/r^2, t_fb = r/|u|, t_fb' = (q.u)/(r|u|)(1 + mu/(r|u|^2)),
+ * u = v_i - v_j; a term with a non-positive denominator (or |u| = 0 for the
+ * fly-by term) gives +INF; r^2 == 0 gives 0.
+ * pi, pj: device int32[npairs] in [0,n); tau_out: device double[npairs].
+ * npairs == 0 is a no-op.  Asynchronous. */
+int cc_pair_timesteps(cc_ctx *ctx, const cc_state *s, int64_t n,
+                      const int32_t *pi, const int32_t *pj, int64_t npairs,
+                      double *tau_out, void *stream);
+
+/* Connected components of the time-step graph with an edge (i,j) iff
+ * tau(i,j) < h (eq. 20, Sec. 2.2-2.3).  label_out (device int32[n]) receives
+ * for each particle the smallest particle index of its component; a particle
+ * is a trivial component iff no other particle shares its label.  If
+ * n_nontrivial_out is not NULL it receives the number of components with at
+ * least two particles (host int64; the call then syncs on `stream`).
+ * h must be > 0 and finite. */
+int cc_split_labels(cc_ctx *ctx, const cc_state *s, int64_t n, double h,
+                    int32_t *label_out, int64_t *n_nontrivial_out, void *stream);
+
+/* Kick operator K_h (eqs. 8-9) for every unordered pair i<j with
+ * label[i] != label[j] (label: device int32[n], or NULL for every pair):
+ *   v_i += h * sum_j G m_j (q_j - q_i) / (|q_j - q_i|^2 + eps^2)^(3/2),
+ * each particle's sum taken over j in ascending index order.  Fails with
+ * CC_ERR_NONFINITE (state untouched) if a kicked pair has r^2 + eps^2 == 0;
+ * the call then syncs. Otherwise asynchronous. */
+int cc_kick(cc_ctx *ctx, cc_state *s, int64_t n, const int32_t *label, double h, void *stream);
+
+/* Drift operator D_h (eq. 6): q_i += h v_i for every i with mask[i] != 0
+ * (mask: device uint8[n], or NULL for every particle).  Asynchronous. */
+int cc_drift(cc_ctx *ctx, cc_state *s, int64_t n, const uint8_t *mask, double h, void *stream);
+
+/* The CC integrator (eqs. 26-31, Fig. 2): t_end/dt global steps of
+ *   evolve_cc(H, h): split at h; evolve_cc(C_k, h/2) for every non-trivial
+ *   component; drift R by h/2; kick every pair in different components by h;
+ *   drift R by h/2; evolve_cc(C_k, h/2) again with the same partition,
+ * starting with h = dt on all n particles.  dt > 0, t_end/dt a positive
+ * integer (t_end is the duration).  Updates x..vz in place; syncs.
+ * On error the state is restored to the start of the failing global step and
+ * out->t_reached tells how far the integration got.  out may be NULL. */
+int cc_evolve(cc_ctx *ctx, cc_state *s, int64_t n, double dt, double t_end,
+              cc_stats *out, void *stream);
+
+/* Independent clusters: particles [offsets[c], offsets[c+1]) form cluster c
+ * (offsets: host int64[ncl+1], strictly increasing, offsets[0] = 0), each
+ * integrated as by cc_evolve with no forces between clusters.
+ * out_per_cluster: host array of ncl records (may be NULL).  Syncs.  On error
+ * every cluster is restored to the start of the failing global step. */
+int cc_evolve_batch(cc_ctx *ctx, cc_state *s, const int64_t *offsets, int32_t ncl,
+                    double dt, double t_end, cc_stats *out_per_cluster, void *stream);
+
+/* Integrals of motion (eqs. 1-3) with compensated FP64 sums, written to the
+ * host array out[12]: kinetic, potential, P[3], L[3], centre of mass[3], total
+ * mass.  Syncs. */
+int cc_diagnostics(cc_ctx *ctx, const cc_state *s, int64_t n, double *out, void *stream);
+
+/* Per-kernel timing for roofline reporting.  While enabled, every launch made
+ * by cc_evolve / cc_evolve_batch is bracketed by HIP events on its stream and
+ * the pair time steps and kicked pairs it processed are counted per kernel
+ * family. */
+typedef struct {
+    char name[32];          /* kernel family */
+    uint64_t launches;
+    double ms;              /* summed event time of the family's launches */
+    uint64_t tau_pairs;     /* pair time steps evaluated by the family */
+    uint64_t kick_pairs;    /* unordered pairs kicked by the family */
+} cc_kernel_time;
+
+/* Enable (1) or disable (0) timing; enabling clears the record.  Syncs. */
+int cc_timing_enable(cc_ctx *ctx, int32_t enable);
+/* Copies up to max records (host array) and returns how many families exist.
+ * Syncs. */
+int cc_timing_report(cc_ctx *ctx, cc_kernel_time *out, int32_t max);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,939 @@
+// cc_api.cpp -- host runtime and C ABI of the CC integrator (include/cc.h).
+//
+// cc_evolve keeps a working copy of the state.  One global step runs
+// evolve_cc(all, dt) (Fig. 2):
+//   * sets larger than the on-chip limit are split by grid-wide kernels
+//     (star test, all-pairs sweep with union-find, labels, a stable sort by
+//     label that makes every component contiguous), their sub-components are
+//     evolved for h/2 -- two-particle ones by the pair kernel, small ones by
+//     the on-chip kernel, large ones by recursing here -- and the level's
+//     drift/kick/drift runs between the two halves in the level's entry order;
+//   * every level restores its entry slot order before it returns, so each
+//     set is always visited in ascending particle index and every kick sums
+//     its partners in the same order as a sequential i<j sweep.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/cc.h"
+#include "cc_device.h"
+#include "cc_launch.h"
+
+using namespace ccg;
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int DEFAULT_SMALL_MAX = 256;
+
+// kernel families for timing
+enum Fam { F_STAR, F_SWEEP, F_LABEL, F_SORT, F_PERMUTE, F_DRIFT, F_KICK, F_PAIRS, F_SMALL, F_VALIDATE, F_OTHER, F_N };
+const char *fam_name[F_N] = {"star", "sweep", "label", "sort", "permute", "drift",
+                             "kick", "pairs", "small", "validate", "other"};
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Level {
+    size_t cap_n = 0, cap_seg = 0;
+    int32_t *label = nullptr;
+    uint8_t *sing = nullptr;
+    int32_t *labp = nullptr;   // label of the particle at each slot, component-contiguous order
+    uint8_t *singp = nullptr;  // singleton flag, component-contiguous order
+    uint32_t *src = nullptr;
+    Seg *pairs = nullptr;
+    Seg *small[4] = {nullptr, nullptr, nullptr, nullptr};
+    Seg *big = nullptr;
+    int32_t *count = nullptr;    // 8 ints
+    int32_t *notstar = nullptr;  // cap_seg
+    Seg *seg = nullptr;
+    int32_t *offs = nullptr;     // 5 arrays of cap_seg+1: chunk, tile, act, kick prefixes, kick groups
+    // pinned host staging
+    Seg *h_seg = nullptr;
+    int32_t *h_offs = nullptr;
+    int32_t *h_count = nullptr;
+    Seg *h_big = nullptr;
+    int32_t *h_notstar = nullptr;
+    int cap_big = 0, cap_small = 0, cap_pairs = 0;
+};
+
+struct TimedRec {
+    int fam;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct cc_ctx {
+    int device = 0;
+    cc_params params{};
+    std::string err;
+    hipStream_t st = nullptr;
+    int cus = 256;
+    size_t cap = 0;
+    size_t cap_cl = 0;
+    // working state
+    double *w[7] = {};
+    int32_t *orig = nullptr;
+    double *snap[6] = {};
+    double *tmp[7] = {};
+    int32_t *tmp_orig = nullptr, *tmp_lab = nullptr;
+    uint32_t *keys = nullptr, *keys_out = nullptr, *vals = nullptr;
+    void *sort_temp = nullptr;
+    size_t sort_bytes = 0;
+    int32_t *parent = nullptr, *cnt = nullptr;
+    uint64_t *stats = nullptr;
+    uint64_t *h_stats = nullptr;
+    int32_t *errf = nullptr;
+    int32_t *h_err = nullptr;
+    int32_t *qhead = nullptr;
+    double *kick_acc = nullptr;  // 3*cap for cc_kick
+    double *kick_part = nullptr; // partial accelerations of the tiled kick
+    size_t kick_part_cap = 0;    // in kick blocks
+    double *diag_part = nullptr;
+    size_t diag_cap = 0;
+    double *diag_out = nullptr, *h_diag = nullptr;
+    std::vector<Level> levels;
+    // timing
+    bool timing = false;
+    std::vector<TimedRec> recs;
+    std::vector<hipEvent_t> ev_pool;
+    double fam_ms[F_N] = {};
+    uint64_t fam_launch[F_N] = {};
+    uint64_t *fam_work = nullptr;  // device counters [F_N][2] (tau pairs, kick pairs)
+};
+
+namespace {
+
+int fail(cc_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(c, e_ == hipErrorOutOfMemory ? CC_ERR_OOM : CC_ERR_DEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                         \
+    } while (0)
+
+#define RC(expr)                 \
+    do {                         \
+        int r_ = (expr);         \
+        if (r_ != CC_OK) return r_; \
+    } while (0)
+
+DevParams dev_params(const cc_ctx *c)
+{
+    DevParams p{};
+    p.eta = c->params.eta;
+    p.eps2 = c->params.eps2;
+    p.G = c->params.G;
+    p.max_depth = c->params.max_depth;
+    return p;
+}
+
+int small_max(const cc_ctx *c) { return c->params.small_max > 0 ? c->params.small_max : DEFAULT_SMALL_MAX; }
+
+int check_params(cc_ctx *c, const cc_params *p)
+{
+    if (!p) return fail(c, CC_ERR_ARG, "params is NULL");
+    if (!(p->eta > 0.0) || !(p->eta <= 1.0)) return fail(c, CC_ERR_ARG, "eta must be in (0, 1]");
+    if (!(p->eps2 >= 0.0) || !std::isfinite(p->eps2)) return fail(c, CC_ERR_ARG, "eps2 must be finite and >= 0");
+    if (!(p->G > 0.0) || !std::isfinite(p->G)) return fail(c, CC_ERR_ARG, "G must be finite and > 0");
+    if (p->max_depth < 0 || p->max_depth > 60) return fail(c, CC_ERR_ARG, "max_depth must be in [0, 60]");
+    if (p->precision != CC_FP64 && p->precision != CC_MIXED) return fail(c, CC_ERR_ARG, "unknown precision");
+    if (p->small_max != 0 && (p->small_max < 3 || p->small_max > 1024))
+        return fail(c, CC_ERR_ARG, "small_max must be 0 or in [3, 1024]");
+    if (p->kick_order != CC_ORDER_FAST && p->kick_order != CC_ORDER_EXACT)
+        return fail(c, CC_ERR_ARG, "unknown kick_order");
+    return CC_OK;
+}
+
+template <class T>
+int dalloc(cc_ctx *c, T **p, size_t count)
+{
+    if (*p) {
+        hipFree(*p);
+        *p = nullptr;
+    }
+    if (count == 0) count = 1;
+    HIPCHK(hipMalloc((void **)p, count * sizeof(T)));
+    return CC_OK;
+}
+
+template <class T>
+int halloc(cc_ctx *c, T **p, size_t count)
+{
+    if (*p) {
+        hipHostFree(*p);
+        *p = nullptr;
+    }
+    if (count == 0) count = 1;
+    HIPCHK(hipHostMalloc((void **)p, count * sizeof(T), hipHostMallocDefault));
+    return CC_OK;
+}
+
+int ensure_capacity(cc_ctx *c, size_t n, size_t ncl)
+{
+    if (n > (size_t)0x3FFFFFFF) return fail(c, CC_ERR_ARG, "n = %zu exceeds the supported 2^30", n);
+    if (n > c->cap) {
+        size_t cap = std::max(n, (size_t)1024);
+        for (int a = 0; a < 7; ++a) RC(dalloc(c, &c->w[a], cap));
+        for (int a = 0; a < 6; ++a) RC(dalloc(c, &c->snap[a], cap));
+        for (int a = 0; a < 7; ++a) RC(dalloc(c, &c->tmp[a], cap));
+        RC(dalloc(c, &c->orig, cap));
+        RC(dalloc(c, &c->tmp_orig, cap));
+        RC(dalloc(c, &c->tmp_lab, cap));
+        RC(dalloc(c, &c->keys, cap));
+        RC(dalloc(c, &c->keys_out, cap));
+        RC(dalloc(c, &c->vals, cap));
+        RC(dalloc(c, &c->parent, cap));
+        RC(dalloc(c, &c->cnt, cap));
+        RC(dalloc(c, &c->kick_acc, 3 * cap));
+        size_t sb = sort_temp_bytes((int)cap);
+        if (c->sort_temp) hipFree(c->sort_temp);
+        c->sort_temp = nullptr;
+        HIPCHK(hipMalloc(&c->sort_temp, sb ? sb : 1));
+        c->sort_bytes = sb;
+        c->cap = cap;
+        for (auto &lv : c->levels) lv.cap_n = 0;  // reallocate lazily
+    }
+    if (ncl > c->cap_cl) {
+        size_t cl = std::max(ncl, (size_t)1);
+        RC(dalloc(c, &c->stats, cl * ST_N));
+        RC(halloc(c, &c->h_stats, cl * ST_N));
+        c->cap_cl = cl;
+    }
+    return CC_OK;
+}
+
+int ensure_level(cc_ctx *c, int k, size_t nseg)
+{
+    if (k >= (int)c->levels.size()) return fail(c, CC_ERR_DEPTH, "grid recursion deeper than %d levels", k);
+    Level &lv = c->levels[k];
+    const size_t n = c->cap;
+    if (lv.cap_n < n) {
+        const int sm = small_max(c);
+        RC(dalloc(c, &lv.label, n));
+        RC(dalloc(c, &lv.sing, n));
+        RC(dalloc(c, &lv.labp, n));
+        RC(dalloc(c, &lv.singp, n));
+        RC(dalloc(c, &lv.src, n));
+        lv.cap_pairs = (int)(n / 2 + 1);
+        lv.cap_small = (int)(n / 3 + 1);
+        lv.cap_big = (int)(n / (size_t)(sm + 1) + 1);
+        RC(dalloc(c, &lv.pairs, lv.cap_pairs));
+        for (int b = 0; b < 4; ++b) RC(dalloc(c, &lv.small[b], lv.cap_small));
+        RC(dalloc(c, &lv.big, lv.cap_big));
+        RC(dalloc(c, &lv.count, 8));
+        RC(halloc(c, &lv.h_count, 8));
+        RC(halloc(c, &lv.h_big, lv.cap_big));
+        lv.cap_n = n;
+    }
+    if (lv.cap_seg < nseg) {
+        const size_t cs = std::max(nseg, (size_t)64);
+        RC(dalloc(c, &lv.notstar, cs));
+        RC(dalloc(c, &lv.seg, cs));
+        RC(dalloc(c, &lv.offs, 5 * (cs + 1)));
+        RC(halloc(c, &lv.h_seg, cs));
+        RC(halloc(c, &lv.h_offs, 5 * (cs + 1)));
+        RC(halloc(c, &lv.h_notstar, cs));
+        lv.cap_seg = cs;
+    }
+    return CC_OK;
+}
+
+SoA work_soa(cc_ctx *c)
+{
+    return SoA{c->w[0], c->w[1], c->w[2], c->w[3], c->w[4], c->w[5], c->w[6], c->orig};
+}
+
+SoA user_soa(const cc_state *s)
+{
+    return SoA{s->x, s->y, s->z, s->vx, s->vy, s->vz, const_cast<double *>(s->m), nullptr};
+}
+
+// ---- timing ----
+hipEvent_t get_event(cc_ctx *c)
+{
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Span {
+    cc_ctx *c;
+    int fam;
+    hipEvent_t a = nullptr;
+    Span(cc_ctx *cc, int f) : c(cc), fam(f)
+    {
+        if (c->timing) {
+            a = get_event(c);
+            if (a) hipEventRecord(a, c->st);
+        }
+    }
+    ~Span()
+    {
+        if (c->timing && a) {
+            hipEvent_t b = get_event(c);
+            if (b) {
+                hipEventRecord(b, c->st);
+                c->recs.push_back({fam, a, b});
+            }
+        }
+    }
+};
+
+void flush_timing(cc_ctx *c)
+{
+    if (c->recs.empty()) return;
+    hipStreamSynchronize(c->st);
+    for (auto &r : c->recs) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.a, r.b);
+        c->fam_ms[r.fam] += ms;
+        c->fam_launch[r.fam]++;
+        c->ev_pool.push_back(r.a);
+        c->ev_pool.push_back(r.b);
+    }
+    c->recs.clear();
+}
+
+uint64_t *fam_ptr(cc_ctx *c, int f) { return (c->timing && c->fam_work) ? c->fam_work + 2 * f : nullptr; }
+
+// ---- grid-level recursion ----
+
+int sync_read_err(cc_ctx *c)
+{
+    HIPCHK(hipMemcpyAsync(c->h_err, c->errf, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return CC_OK;
+}
+
+int err_code(cc_ctx *c, int bits)
+{
+    if (bits & EB_MASS) return fail(c, CC_ERR_ARG, "a mass is not finite and positive");
+    if (bits & EB_NONFINITE) return fail(c, CC_ERR_NONFINITE, "non-finite state or zero separation in a kick");
+    if (bits & EB_DEPTH) return fail(c, CC_ERR_DEPTH, "recursion deeper than max_depth = %d", c->params.max_depth);
+    if (bits & EB_CAPACITY) return fail(c, CC_ERR_DEVICE, "internal work-list capacity exceeded");
+    if (bits & EB_BUDGET)
+        return fail(c, CC_ERR_DEPTH, "a component needed more than the per-launch work budget of halvings");
+    return CC_OK;
+}
+
+int run_small_and_pairs(cc_ctx *c, Level &lv, double H, int n_pairs, int n_small)
+{
+    const DevParams p = dev_params(c);
+    SoA W = work_soa(c);
+    if (n_pairs > 0) {
+        Span s(c, F_PAIRS);
+        HIPCHK(launch_pairs(W, lv.pairs, lv.count, lv.cap_pairs, n_pairs, H, p, c->errf, c->stats, fam_ptr(c, F_PAIRS),
+                            c->st));
+    }
+    if (n_small > 0) {
+        HIPCHK(launch_fill_i32(c->qhead, 1, 0, c->st));
+        SmallArgs sa{};
+        for (int b = 0; b < 4; ++b) sa.bin[b] = lv.small[b];
+        sa.count = lv.count + 1;
+        sa.cap = lv.cap_small;
+        sa.qhead = c->qhead;
+        const int sm = small_max(c);
+        const size_t lds = small_lds_bytes(sm);
+        int per_cu = (int)std::min<size_t>(8, std::max<size_t>(1, (160 * 1024) / (lds + 1024)));
+        const int nblk = std::min(n_small, c->cus * per_cu);
+        Span s(c, F_SMALL);
+        HIPCHK(launch_small(W, sa, sm, c->params.kick_order == CC_ORDER_EXACT, H, p, c->errf, c->stats,
+                            fam_ptr(c, F_SMALL), nblk, c->st));
+    }
+    return CC_OK;
+}
+
+int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h);
+
+// Items of one list of independent sets at level depth: route by size.
+int dispatch_sets(cc_ctx *c, int k, Level &lv, double H, const std::vector<Seg> &big, int n_pairs, int n_small)
+{
+    RC(run_small_and_pairs(c, lv, H, n_pairs, n_small));
+    if (!big.empty()) RC(evolve_grid(c, k + 1, big, H));
+    return CC_OK;
+}
+
+int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
+{
+    if (segs.empty()) return CC_OK;
+    if (segs[0].depth > c->params.max_depth)
+        return fail(c, CC_ERR_DEPTH, "recursion deeper than max_depth = %d", c->params.max_depth);
+    const int nseg = (int)segs.size();
+    RC(ensure_level(c, k, nseg));
+    Level &lv = c->levels[k];
+    const DevParams p = dev_params(c);
+    SoA W = work_soa(c);
+
+    // segment descriptors and prefix arrays
+    const size_t S1 = (size_t)nseg + 1;
+    int32_t *chunk = lv.h_offs, *tile = lv.h_offs + S1, *act = lv.h_offs + 2 * S1, *koff = lv.h_offs + 3 * S1,
+            *kgrp = lv.h_offs + 4 * S1;
+    chunk[0] = tile[0] = act[0] = koff[0] = 0;
+    int64_t totT = 0;
+    for (int s = 0; s < nseg; ++s) totT += (segs[s].n + TPB - 1) / TPB;
+    // enough (i tile, j group) blocks to fill the chip several times over
+    const int64_t gtarget = std::max<int64_t>(1, (8 * (int64_t)c->cus + totT - 1) / totT);
+    for (int s = 0; s < nseg; ++s) {
+        lv.h_seg[s] = segs[s];
+        const int n = segs[s].n;
+        const int64_t T = (n + TPB - 1) / TPB;
+        const int64_t G = std::min<int64_t>(T, gtarget);
+        const int64_t nt = tile[s] + T * (T + 1) / 2, nk = koff[s] + T * G;
+        if (nt > INT32_MAX || nk > INT32_MAX) return fail(c, CC_ERR_ARG, "set of %d particles is too large", n);
+        chunk[s + 1] = chunk[s] + (int32_t)T;
+        tile[s + 1] = (int32_t)nt;
+        act[s + 1] = act[s] + n;
+        koff[s + 1] = (int32_t)nk;
+        kgrp[s] = (int32_t)G;
+    }
+    HIPCHK(hipMemcpyAsync(lv.seg, lv.h_seg, nseg * sizeof(Seg), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(lv.offs, lv.h_offs, 5 * S1 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+    GridLevelArgs a{lv.seg, lv.offs, lv.offs + S1, lv.offs + 2 * S1, lv.offs + 3 * S1, lv.offs + 4 * S1,
+                    nseg, chunk[nseg], tile[nseg], act[nseg], koff[nseg]};
+    const bool exact = c->params.kick_order == CC_ORDER_EXACT;
+    if (!exact && (size_t)a.nkblocks > c->kick_part_cap) {
+        RC(dalloc(c, &c->kick_part, (size_t)a.nkblocks * 3 * TPB));
+        c->kick_part_cap = a.nkblocks;
+    }
+    HIPCHK(launch_fill_i32(lv.notstar, nseg, 0, c->st));
+    HIPCHK(launch_fill_i32(lv.count, 8, 0, c->st));
+    {
+        Span s(c, F_STAR);
+        HIPCHK(launch_star(W, a, lv.notstar, c->parent, c->cnt, p, h, c->stats, fam_ptr(c, F_STAR), c->st));
+    }
+    {
+        Span s(c, F_SWEEP);
+        HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, c->stats, fam_ptr(c, F_SWEEP), c->st));
+    }
+    {
+        Span s(c, F_LABEL);
+        HIPCHK(launch_label(a, lv.notstar, c->parent, lv.label, c->cnt, c->stats, c->st));
+        HIPCHK(launch_keys(a, lv.label, c->keys, c->vals, c->st));
+    }
+    int bits = 0;
+    {
+        int maxslot = 1;
+        for (int s = 0; s < nseg; ++s) maxslot = std::max(maxslot, segs[s].start + segs[s].n);
+        int end_bit = 1;
+        while ((1 << end_bit) < maxslot + 1 && end_bit < 31) end_bit++;
+        Span s(c, F_SORT);
+        HIPCHK(launch_sort(c->sort_temp, c->sort_bytes, c->keys, c->keys_out, c->vals, lv.src, a.nact, end_bit, c->st));
+    }
+    TmpArrays T{c->tmp[0], c->tmp[1], c->tmp[2], c->tmp[3], c->tmp[4], c->tmp[5], c->tmp[6], c->tmp_orig, c->tmp_lab};
+    ListArgs L{};
+    L.pairs = lv.pairs;
+    for (int b = 0; b < 4; ++b) L.small[b] = lv.small[b];
+    L.big = lv.big;
+    L.count = lv.count;
+    L.cap_pairs = lv.cap_pairs;
+    L.cap_small = lv.cap_small;
+    L.cap_big = lv.cap_big;
+    L.small_max = small_max(c);
+    L.bin_lim[0] = 8;
+    L.bin_lim[1] = 32;
+    L.bin_lim[2] = 128;
+    L.labp = exact ? nullptr : lv.labp;
+    L.singp = exact ? nullptr : lv.singp;
+    {
+        Span s(c, F_PERMUTE);
+        HIPCHK(launch_permute(W, T, a, lv.src, lv.label, c->cnt, lv.sing, &L, c->stats, false, c->st));
+    }
+    HIPCHK(hipMemcpyAsync(lv.h_count, lv.count, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(lv.h_big, lv.big, lv.cap_big * sizeof(Seg), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(c->h_err, c->errf, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    bits = *c->h_err;
+    if (bits) return err_code(c, bits);
+    const int n_pairs = lv.h_count[0];
+    const int n_small = lv.h_count[1] + lv.h_count[2] + lv.h_count[3] + lv.h_count[4];
+    const int n_big = lv.h_count[5];
+    if (n_pairs > lv.cap_pairs || lv.h_count[1] > lv.cap_small || lv.h_count[2] > lv.cap_small ||
+        lv.h_count[3] > lv.cap_small || lv.h_count[4] > lv.cap_small || n_big > lv.cap_big)
+        return fail(c, CC_ERR_DEVICE, "internal work-list capacity exceeded");
+    std::vector<Seg> big(lv.h_big, lv.h_big + n_big);
+    std::sort(big.begin(), big.end(), [](const Seg &x, const Seg &y) { return x.start < y.start; });
+    const bool any_sub = (n_pairs + n_small + n_big) > 0;
+    const double H = 0.5 * h;
+
+    if (!exact) {
+        // Component-contiguous order throughout: first half, drift/kick/drift
+        // of the level, second half, then back to the entry order.
+        if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
+        Level &lv2 = c->levels[k];
+        {
+            Span s(c, F_DRIFT);
+            HIPCHK(launch_drift_seg(W, a, lv2.singp, H, c->stats, c->st));
+        }
+        {
+            Span s(c, F_KICK);
+            HIPCHK(launch_kick_tiles(W, a, lv2.labp, h, c->params.eps2, c->params.G, c->kick_part, c->errf, c->stats,
+                                     fam_ptr(c, F_KICK), c->st));
+        }
+        {
+            Span s(c, F_DRIFT);
+            HIPCHK(launch_drift_seg(W, a, lv2.singp, H, c->stats, c->st));
+        }
+        if (any_sub) {
+            RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
+            Level &lv3 = c->levels[k];
+            Span s(c, F_PERMUTE);
+            HIPCHK(launch_permute(W, T, a, lv3.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
+        }
+        return CC_OK;
+    }
+
+    // Exact order: the level's drift/kick/drift runs in the entry order, in
+    // which every set is ascending in particle index.
+    if (any_sub) {
+        RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
+        Level &lv2 = c->levels[k];
+        Span s(c, F_PERMUTE);
+        HIPCHK(launch_permute(W, T, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
+    }
+    {
+        Level &lv2 = c->levels[k];
+        {
+            Span s(c, F_DRIFT);
+            HIPCHK(launch_drift_seg(W, a, lv2.sing, H, c->stats, c->st));
+        }
+        {
+            Span s(c, F_KICK);
+            HIPCHK(launch_kick_seg(W, a, lv2.label, h, c->params.eps2, c->params.G, c->errf, c->stats,
+                                   fam_ptr(c, F_KICK), c->st));
+        }
+        {
+            Span s(c, F_DRIFT);
+            HIPCHK(launch_drift_seg(W, a, lv2.sing, H, c->stats, c->st));
+        }
+    }
+    // second half with the same partition
+    if (any_sub) {
+        {
+            Level &lv2 = c->levels[k];
+            Span s(c, F_PERMUTE);
+            HIPCHK(launch_permute(W, T, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, false, c->st));
+        }
+        RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
+        Level &lv2 = c->levels[k];
+        Span s(c, F_PERMUTE);
+        HIPCHK(launch_permute(W, T, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
+    }
+    return CC_OK;
+}
+
+// One global step on a list of top-level sets (clusters), all at depth 0.
+int global_step(cc_ctx *c, const std::vector<Seg> &top, double dt)
+{
+    // Route top-level sets: small ones straight to the on-chip / pair kernels
+    // through level-0 work lists; large ones to the grid recursion.
+    std::vector<Seg> big, pairs, small[4];
+    const int sm = small_max(c);
+    for (const Seg &g : top) {
+        if (g.n == 2) pairs.push_back(g);
+        else if (g.n <= sm) {
+            const int b = g.n <= 8 ? 0 : g.n <= 32 ? 1 : g.n <= 128 ? 2 : 3;
+            small[b].push_back(g);
+        } else big.push_back(g);
+    }
+    if (!pairs.empty() || !small[0].empty() || !small[1].empty() || !small[2].empty() || !small[3].empty()) {
+        // a pseudo-level above 0 holds the routed lists
+        const int k = 0;
+        RC(ensure_level(c, k, 1));
+        Level &lv = c->levels[k];
+        int32_t cnts[8] = {0};
+        cnts[0] = (int)pairs.size();
+        for (int b = 0; b < 4; ++b) cnts[1 + b] = (int)small[b].size();
+        for (int b = 0; b < 8; ++b) lv.h_count[b] = cnts[b];
+        HIPCHK(hipMemcpyAsync(lv.count, lv.h_count, 8 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+        if (!pairs.empty())
+            HIPCHK(hipMemcpyAsync(lv.pairs, pairs.data(), pairs.size() * sizeof(Seg), hipMemcpyHostToDevice, c->st));
+        for (int b = 0; b < 4; ++b)
+            if (!small[b].empty())
+                HIPCHK(hipMemcpyAsync(lv.small[b], small[b].data(), small[b].size() * sizeof(Seg),
+                                      hipMemcpyHostToDevice, c->st));
+        const int ns = (int)(small[0].size() + small[1].size() + small[2].size() + small[3].size());
+        RC(run_small_and_pairs(c, lv, dt, (int)pairs.size(), ns));
+        // the host vectors must outlive the async copies
+        HIPCHK(hipStreamSynchronize(c->st));
+    }
+    if (!big.empty()) RC(evolve_grid(c, 0, big, dt));
+    return CC_OK;
+}
+
+int check_state_ptrs(cc_ctx *c, const cc_state *s)
+{
+    if (!s) return fail(c, CC_ERR_ARG, "state is NULL");
+    if (!s->x || !s->y || !s->z || !s->vx || !s->vy || !s->vz || !s->m)
+        return fail(c, CC_ERR_ARG, "a state pointer is NULL");
+    return CC_OK;
+}
+
+int step_count(cc_ctx *c, double dt, double t_end, int64_t *nsteps)
+{
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, CC_ERR_ARG, "dt must be finite and > 0");
+    if (!(t_end > 0.0) || !std::isfinite(t_end)) return fail(c, CC_ERR_ARG, "t_end must be finite and > 0");
+    const double q = t_end / dt;
+    if (!(q >= 1.0) || q != std::floor(q) || q > 2147483647.0)
+        return fail(c, CC_ERR_ARG, "t_end/dt = %.17g is not a positive integer", q);
+    *nsteps = (int64_t)q;
+    return CC_OK;
+}
+
+int evolve_common(cc_ctx *c, cc_state *s, int64_t n, const int64_t *off, int32_t ncl, double dt, double t_end,
+                  cc_stats *out, void *stream)
+{
+    c->err.clear();
+    RC(check_state_ptrs(c, s));
+    int64_t nsteps = 0;
+    RC(step_count(c, dt, t_end, &nsteps));
+    if (n < 1) return fail(c, CC_ERR_ARG, "n must be >= 1");
+    std::vector<Seg> top;
+    for (int32_t k = 0; k < ncl; ++k) {
+        const int64_t a = off[k], b = off[k + 1];
+        if (a < 0 || b <= a || b > n) return fail(c, CC_ERR_ARG, "offsets must be strictly increasing in [0, n]");
+        top.push_back(Seg{(int32_t)a, (int32_t)(b - a), k, 0});
+    }
+    HIPCHK(hipSetDevice(c->device));
+    c->st = (hipStream_t)stream;
+    RC(ensure_capacity(c, (size_t)n, (size_t)ncl));
+    HIPCHK(hipMemsetAsync(c->stats, 0, (size_t)ncl * ST_N * sizeof(uint64_t), c->st));
+    const size_t bytes = (size_t)n * sizeof(double);
+    double *user[7] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, const_cast<double *>(s->m)};
+    for (int a = 0; a < 7; ++a) HIPCHK(hipMemcpyAsync(c->w[a], user[a], bytes, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(launch_iota(c->orig, n, c->st));
+    int rc = CC_OK;
+    int64_t done = 0;
+    for (int64_t step = 0; step < nsteps; ++step) {
+        HIPCHK(launch_fill_i32(c->errf, 1, 0, c->st));
+        {
+            Span sp(c, F_VALIDATE);
+            HIPCHK(launch_validate(c->w[0], c->w[1], c->w[2], c->w[3], c->w[4], c->w[5], c->w[6], n, c->errf, c->st));
+        }
+        for (int a = 0; a < 6; ++a) HIPCHK(hipMemcpyAsync(c->snap[a], c->w[a], bytes, hipMemcpyDeviceToDevice, c->st));
+        RC(sync_read_err(c));
+        if (*c->h_err) {
+            rc = err_code(c, *c->h_err);
+            break;
+        }
+        rc = global_step(c, top, dt);
+        if (rc == CC_OK) {
+            HIPCHK(launch_validate(c->w[0], c->w[1], c->w[2], c->w[3], c->w[4], c->w[5], c->w[6], n, c->errf, c->st));
+            RC(sync_read_err(c));
+            if (*c->h_err) rc = err_code(c, *c->h_err);
+        }
+        if (rc != CC_OK) {
+            hipStreamSynchronize(c->st);
+            for (int a = 0; a < 6; ++a)
+                hipMemcpyAsync(c->w[a], c->snap[a], bytes, hipMemcpyDeviceToDevice, c->st);
+            break;
+        }
+        done = step + 1;
+        if (c->timing) flush_timing(c);
+    }
+    // copy the working state back (slots are in entry order = particle order)
+    for (int a = 0; a < 6; ++a) HIPCHK(hipMemcpyAsync(user[a], c->w[a], bytes, hipMemcpyDeviceToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(c->h_stats, c->stats, (size_t)ncl * ST_N * sizeof(uint64_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    if (c->timing) flush_timing(c);
+    if (out) {
+        for (int32_t k = 0; k < ncl; ++k) {
+            const uint64_t *h = c->h_stats + (size_t)k * ST_N;
+            cc_stats &o = out[k];
+            o.tau_pairs = h[ST_TAU];
+            o.tau_pairs_alg = h[ST_TAU_ALG];
+            o.kick_pairs = h[ST_KICK];
+            o.drifts = h[ST_DRIFT];
+            o.components = h[ST_COMP];
+            o.splits = h[ST_SPLIT];
+            o.max_depth_seen = (int64_t)h[ST_MAXD];
+            o.t_reached = (double)done * dt;
+        }
+    }
+    return rc;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int cc_create(cc_ctx **out, int32_t hip_device, const cc_params *p)
+{
+    if (!out) return CC_ERR_ARG;
+    *out = nullptr;
+    cc_ctx *c = new (std::nothrow) cc_ctx();
+    if (!c) return CC_ERR_OOM;
+    int rc = check_params(c, p);
+    if (rc != CC_OK) {
+        delete c;
+        return rc;
+    }
+    c->params = *p;
+    c->device = hip_device;
+    c->levels.resize(64);  // fixed size: references to levels stay valid during the recursion
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
+        delete c;
+        return CC_ERR_DEVICE;
+    }
+    if (hipSetDevice(hip_device) != hipSuccess) {
+        delete c;
+        return CC_ERR_DEVICE;
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
+        c->cus = cus;
+    if (dalloc(c, &c->errf, 1) != CC_OK || halloc(c, &c->h_err, 1) != CC_OK || dalloc(c, &c->qhead, 1) != CC_OK ||
+        dalloc(c, &c->diag_out, 16) != CC_OK || halloc(c, &c->h_diag, 16) != CC_OK ||
+        dalloc(c, &c->fam_work, 2 * F_N) != CC_OK) {
+        cc_destroy(c);
+        return CC_ERR_OOM;
+    }
+    *out = c;
+    return CC_OK;
+}
+
+void cc_destroy(cc_ctx *c)
+{
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    auto F = [](void *p) {
+        if (p) hipFree(p);
+    };
+    auto FH = [](void *p) {
+        if (p) hipHostFree(p);
+    };
+    for (auto *p : c->w) F(p);
+    for (auto *p : c->snap) F(p);
+    for (auto *p : c->tmp) F(p);
+    F(c->orig); F(c->tmp_orig); F(c->tmp_lab); F(c->keys); F(c->keys_out); F(c->vals); F(c->sort_temp);
+    F(c->parent); F(c->cnt); F(c->stats); F(c->errf); F(c->qhead); F(c->kick_acc); F(c->kick_part); F(c->diag_part);
+    F(c->diag_out); F(c->fam_work);
+    FH(c->h_stats); FH(c->h_err); FH(c->h_diag);
+    for (auto &lv : c->levels) {
+        F(lv.label); F(lv.sing); F(lv.labp); F(lv.singp); F(lv.src); F(lv.pairs);
+        for (auto *p : lv.small) F(p);
+        F(lv.big); F(lv.count); F(lv.notstar); F(lv.seg); F(lv.offs);
+        FH(lv.h_seg); FH(lv.h_offs); FH(lv.h_count); FH(lv.h_big); FH(lv.h_notstar);
+    }
+    for (auto &r : c->recs) {
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    for (auto e : c->ev_pool) hipEventDestroy(e);
+    delete c;
+}
+
+int cc_set_params(cc_ctx *c, const cc_params *p)
+{
+    if (!c) return CC_ERR_ARG;
+    c->err.clear();
+    RC(check_params(c, p));
+    const bool sm_changed = small_max(c) != (p->small_max > 0 ? p->small_max : DEFAULT_SMALL_MAX);
+    c->params = *p;
+    if (sm_changed)
+        for (auto &lv : c->levels) lv.cap_n = 0;
+    return CC_OK;
+}
+
+const char *cc_last_error(const cc_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+int cc_pair_timesteps(cc_ctx *c, const cc_state *s, int64_t n, const int32_t *pi, const int32_t *pj, int64_t npairs,
+                      double *tau_out, void *stream)
+{
+    if (!c) return CC_ERR_ARG;
+    c->err.clear();
+    RC(check_state_ptrs(c, s));
+    if (n < 1 || npairs < 0) return fail(c, CC_ERR_ARG, "n must be >= 1 and npairs >= 0");
+    if (npairs == 0) return CC_OK;
+    if (!pi || !pj || !tau_out) return fail(c, CC_ERR_ARG, "pair or output pointer is NULL");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(launch_pair_tau(user_soa(s), pi, pj, npairs, tau_out, dev_params(c), (hipStream_t)stream));
+    return CC_OK;
+}
+
+int cc_split_labels(cc_ctx *c, const cc_state *s, int64_t n, double h, int32_t *label_out, int64_t *n_nontrivial_out,
+                    void *stream)
+{
+    if (!c) return CC_ERR_ARG;
+    c->err.clear();
+    RC(check_state_ptrs(c, s));
+    if (n < 1) return fail(c, CC_ERR_ARG, "n must be >= 1");
+    if (!label_out) return fail(c, CC_ERR_ARG, "label_out is NULL");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(c, CC_ERR_ARG, "h must be finite and > 0");
+    HIPCHK(hipSetDevice(c->device));
+    c->st = (hipStream_t)stream;
+    RC(ensure_capacity(c, (size_t)n, 1));
+    RC(ensure_level(c, 0, 1));
+    Level &lv = c->levels[0];
+    const int T = (int)((n + TPB - 1) / TPB);
+    lv.h_seg[0] = Seg{0, (int32_t)n, 0, 0};
+    int32_t *o = lv.h_offs;
+    if ((int64_t)T * (T + 1) / 2 > INT32_MAX) return fail(c, CC_ERR_ARG, "n too large");
+    o[0] = 0; o[1] = T; o[2] = 0; o[3] = T * (T + 1) / 2; o[4] = 0; o[5] = (int32_t)n;
+    HIPCHK(hipMemcpyAsync(lv.seg, lv.h_seg, sizeof(Seg), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(lv.offs, lv.h_offs, 6 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+    GridLevelArgs a{lv.seg, lv.offs, lv.offs + 2, lv.offs + 4, nullptr, nullptr, 1, T, T * (T + 1) / 2, (int)n, 0};
+    HIPCHK(hipMemsetAsync(c->stats, 0, ST_N * sizeof(uint64_t), c->st));
+    HIPCHK(launch_fill_i32(lv.notstar, 1, 0, c->st));
+    const DevParams p = dev_params(c);
+    SoA S = user_soa(s);
+    HIPCHK(launch_star(S, a, lv.notstar, c->parent, c->cnt, p, h, c->stats, nullptr, c->st));
+    HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, c->stats, nullptr, c->st));
+    HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, c->cnt, c->stats, c->st));
+    if (n_nontrivial_out) {
+        // roots carry their component size in cnt (zeroed for every slot by the star kernel)
+        std::vector<int32_t> cnt((size_t)n);
+        HIPCHK(hipMemcpyAsync(cnt.data(), c->cnt, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        int64_t nt = 0;
+        for (int64_t i = 0; i < n; ++i) nt += (cnt[(size_t)i] >= 2);
+        *n_nontrivial_out = nt;
+    }
+    return CC_OK;
+}
+
+int cc_kick(cc_ctx *c, cc_state *s, int64_t n, const int32_t *label, double h, void *stream)
+{
+    if (!c) return CC_ERR_ARG;
+    c->err.clear();
+    RC(check_state_ptrs(c, s));
+    if (n < 1) return fail(c, CC_ERR_ARG, "n must be >= 1");
+    if (!std::isfinite(h)) return fail(c, CC_ERR_ARG, "h must be finite");
+    HIPCHK(hipSetDevice(c->device));
+    c->st = (hipStream_t)stream;
+    RC(ensure_capacity(c, (size_t)n, 1));
+    SoA S = user_soa(s);
+    double *ax = c->kick_acc, *ay = ax + c->cap, *az = ay + c->cap;
+    HIPCHK(launch_fill_i32(c->errf, 1, 0, c->st));
+    HIPCHK(launch_kick_all(S, (int)n, label, c->params.eps2, c->params.G, ax, ay, az, c->errf, c->st));
+    RC(sync_read_err(c));
+    if (*c->h_err) return err_code(c, *c->h_err);
+    HIPCHK(launch_apply_kick(S, (int)n, ax, ay, az, h, c->st));
+    return CC_OK;
+}
+
+int cc_drift(cc_ctx *c, cc_state *s, int64_t n, const uint8_t *mask, double h, void *stream)
+{
+    if (!c) return CC_ERR_ARG;
+    c->err.clear();
+    RC(check_state_ptrs(c, s));
+    if (n < 1) return fail(c, CC_ERR_ARG, "n must be >= 1");
+    if (!std::isfinite(h)) return fail(c, CC_ERR_ARG, "h must be finite");
+    HIPCHK(hipSetDevice(c->device));
+    HIPCHK(launch_drift_mask(user_soa(s), n, mask, h, (hipStream_t)stream));
+    return CC_OK;
+}
+
+int cc_evolve(cc_ctx *c, cc_state *s, int64_t n, double dt, double t_end, cc_stats *out, void *stream)
+{
+    if (!c) return CC_ERR_ARG;
+    const int64_t off[2] = {0, n};
+    return evolve_common(c, s, n, off, 1, dt, t_end, out, stream);
+}
+
+int cc_evolve_batch(cc_ctx *c, cc_state *s, const int64_t *offsets, int32_t ncl, double dt, double t_end,
+                    cc_stats *out, void *stream)
+{
+    if (!c) return CC_ERR_ARG;
+    c->err.clear();
+    if (!offsets || ncl < 1) return fail(c, CC_ERR_ARG, "offsets is NULL or ncl < 1");
+    if (offsets[0] != 0) return fail(c, CC_ERR_ARG, "offsets[0] must be 0");
+    return evolve_common(c, s, offsets[ncl], offsets, ncl, dt, t_end, out, stream);
+}
+
+int cc_diagnostics(cc_ctx *c, const cc_state *s, int64_t n, double *out, void *stream)
+{
+    if (!c) return CC_ERR_ARG;
+    c->err.clear();
+    RC(check_state_ptrs(c, s));
+    if (n < 1 || !out) return fail(c, CC_ERR_ARG, "n must be >= 1 and out non-NULL");
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t need = (size_t)diag_blocks((int)n) * 24;
+    if (need > c->diag_cap) {
+        RC(dalloc(c, &c->diag_part, need));
+        c->diag_cap = need;
+    }
+    HIPCHK(launch_diag(user_soa(s), (int)n, c->params.eps2, c->params.G, c->diag_part, c->diag_out, st));
+    HIPCHK(hipMemcpyAsync(c->h_diag, c->diag_out, 12 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double *d = c->h_diag;
+    out[0] = d[0];
+    out[1] = d[1];
+    for (int q = 2; q < 8; ++q) out[q] = d[q];
+    for (int q = 8; q < 11; ++q) out[q] = d[q] / d[11];
+    out[11] = d[11];
+    return CC_OK;
+}
+
+int cc_timing_enable(cc_ctx *c, int32_t enable)
+{
+    if (!c) return CC_ERR_ARG;
+    c->err.clear();
+    HIPCHK(hipSetDevice(c->device));
+    flush_timing(c);
+    c->timing = enable != 0;
+    if (c->timing) {
+        for (int f = 0; f < F_N; ++f) {
+            c->fam_ms[f] = 0.0;
+            c->fam_launch[f] = 0;
+        }
+        HIPCHK(hipMemset(c->fam_work, 0, 2 * F_N * sizeof(uint64_t)));
+    }
+    return CC_OK;
+}
+
+int cc_timing_report(cc_ctx *c, cc_kernel_time *out, int32_t max)
+{
+    if (!c) return CC_ERR_ARG;
+    c->err.clear();
+    HIPCHK(hipSetDevice(c->device));
+    flush_timing(c);
+    uint64_t w[2 * F_N];
+    HIPCHK(hipMemcpy(w, c->fam_work, sizeof w, hipMemcpyDeviceToHost));
+    int k = 0;
+    for (int f = 0; f < F_N; ++f) {
+        if (k < max && out) {
+            std::snprintf(out[k].name, sizeof out[k].name, "%s", fam_name[f]);
+            out[k].launches = c->fam_launch[f];
+            out[k].ms = c->fam_ms[f];
+            out[k].tau_pairs = w[2 * f];
+            out[k].kick_pairs = w[2 * f + 1];
+        }
+        k++;
+    }
+    return k;
+}
+
+}  // extern "C"

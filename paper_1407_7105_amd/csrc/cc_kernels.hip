@@ -1,0 +1,1521 @@
+// cc_kernels.hip -- gfx950 kernels of the CC integrator.
+//
+// Grid-level kernels work on a list of segments (each an evolve_cc call on a
+// contiguous slot range of the working arrays); the on-chip kernel runs the
+// whole recursion of Fig. 2 for a component that fits in one workgroup's LDS;
+// the pair kernel runs two-particle components one per lane.
+#include <hip/hip_runtime.h>
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "cc_device.h"
+#include "cc_launch.h"
+
+namespace ccg {
+
+constexpr int TPB = 256;  // threads per block everywhere (4 wave64)
+
+// Largest s in [0, nseg) with off[s] <= b (off is a prefix-sum array).
+__device__ __forceinline__ int find_seg(const int32_t *off, int nseg, int b)
+{
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void stat_add(uint64_t *stats, int cluster, int idx, uint64_t v)
+{
+    if (v) atomicAdd((unsigned long long *)&stats[(size_t)cluster * ST_N + idx], (unsigned long long)v);
+}
+
+__device__ __forceinline__ void stat_max(uint64_t *stats, int cluster, int32_t d)
+{
+    atomicMax((unsigned long long *)&stats[(size_t)cluster * ST_N + ST_MAXD], (unsigned long long)d);
+}
+
+// Per-kernel-family algorithmic work (tau pairs, kick pairs) for roofline
+// reporting; fam == nullptr when timing is off.
+__device__ __forceinline__ void fam_add(uint64_t *fam, int idx, uint64_t v)
+{
+    if (fam && v) atomicAdd((unsigned long long *)&fam[idx], (unsigned long long)v);
+}
+
+// wave64 sum of a uint64
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide sum to thread 0 (TPB threads).
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh)
+{
+    v = wave_sum_u64(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    uint64_t t = 0;
+    if (threadIdx.x == 0) t = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Global union-find helpers (parent array in global memory, L1 bypassed).
+// The smaller root always becomes the parent, so a tree's root is its
+// smallest slot and the final label is the component's smallest slot.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t gload(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void gstore(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Parent pointers only ever point to smaller slots, so a walk ends within
+// the segment size; the budget only guards against corrupted input.
+__device__ __forceinline__ int32_t gfind(int32_t *par, int32_t a)
+{
+    for (int it = 0; it < FIND_BUDGET; ++it) {
+        const int32_t q = gload(&par[a]);
+        if (q == a) return a;
+        const int32_t g = gload(&par[q]);
+        if (g != q) gstore(&par[a], g);  // path halving: g is an ancestor of a
+        a = q;
+    }
+    return a;
+}
+
+__device__ __forceinline__ int32_t gunite(int32_t *par, int32_t a, int32_t b)
+{
+    for (int it = 0; it < FIND_BUDGET; ++it) {
+        a = gfind(par, a);
+        b = gfind(par, b);
+        if (a == b) return a;
+        if (a > b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(&par[b], b, a) == b) return a;
+    }
+    return a;
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise kernels
+// ---------------------------------------------------------------------------
+__global__ void k_validate(const double *__restrict__ x, const double *__restrict__ y,
+                           const double *__restrict__ z, const double *__restrict__ vx,
+                           const double *__restrict__ vy, const double *__restrict__ vz,
+                           const double *__restrict__ m, int64_t n, int32_t *err)
+{
+    int bits = 0;
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+        if (!(m[i] > 0.0) || !isfinite(m[i])) bits |= EB_MASS;
+        if (!isfinite(x[i]) || !isfinite(y[i]) || !isfinite(z[i]) || !isfinite(vx[i]) || !isfinite(vy[i]) ||
+            !isfinite(vz[i]))
+            bits |= EB_NONFINITE;
+    }
+    if (bits) atomicOr(err, bits);
+}
+
+__global__ void k_pair_tau(SoA S, const int32_t *__restrict__ pi, const int32_t *__restrict__ pj,
+                           int64_t npairs, double *__restrict__ out, DevParams p)
+{
+    for (int64_t k = blockIdx.x * (int64_t)TPB + threadIdx.x; k < npairs; k += (int64_t)gridDim.x * TPB) {
+        const int32_t i = pi[k], j = pj[k];
+        out[k] = tau_pair(S.x[i] - S.x[j], S.y[i] - S.y[j], S.z[i] - S.z[j], S.vx[i] - S.vx[j],
+                          S.vy[i] - S.vy[j], S.vz[i] - S.vz[j], S.m[i] + S.m[j], p);
+    }
+}
+
+__global__ void k_drift_mask(SoA S, int64_t n, const uint8_t *__restrict__ mask, double h)
+{
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+        if (mask && !mask[i]) continue;
+        S.x[i] += h * S.vx[i];
+        S.y[i] += h * S.vy[i];
+        S.z[i] += h * S.vz[i];
+    }
+}
+
+__global__ void k_iota(int32_t *a, int64_t n)
+{
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB)
+        a[i] = (int32_t)i;
+}
+
+__global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) a[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Grid-level split.  Segments are described by prefix arrays over slot
+// chunks of TPB (chunk_off) and over triangular tile pairs (tile_off).
+// ---------------------------------------------------------------------------
+
+// Star test (Sec. 2.3, fully connected case): with X the segment's first slot,
+// the segment is one component if tau(X,U) < h for every other U.  notstar[s]
+// is set when some U fails.  Also initialises the union-find arrays.
+__global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg,
+                                               const int32_t *__restrict__ chunk_off, int nseg,
+                                               int32_t *__restrict__ notstar, int32_t *__restrict__ parent,
+                                               int32_t *__restrict__ cnt, DevParams p, double h,
+                                               uint64_t *stats, uint64_t *fam)
+{
+    __shared__ uint64_t sh[4];
+    const int s = find_seg(chunk_off, nseg, blockIdx.x);
+    const Seg g = seg[s];
+    const int local = (blockIdx.x - chunk_off[s]) * TPB + threadIdx.x;
+    const int X = g.start;
+    uint64_t ev = 0;
+    if (local < g.n) {
+        const int u = g.start + local;
+        parent[u] = u;
+        cnt[u] = 0;
+        if (local > 0) {
+            ev = 1;
+            if (!edge_pair(S.x[X] - S.x[u], S.y[X] - S.y[u], S.z[X] - S.z[u], S.vx[X] - S.vx[u],
+                           S.vy[X] - S.vy[u], S.vz[X] - S.vz[u], S.m[X] + S.m[u], p, h))
+                notstar[s] = 1;
+        }
+    }
+    const uint64_t t = block_sum_u64(ev, sh);
+    if (threadIdx.x == 0) {
+        stat_add(stats, g.cluster, ST_TAU, t);
+        fam_add(fam, 0, t);
+    }
+}
+
+// All-pairs sweep of a segment that failed the star test: for each pair
+// i<j with tau(i,j) < h, merge their sets.  One block per (i-tile, j-tile)
+// with i-tile <= j-tile; the j tile is staged in LDS together with each j's
+// set root at load time, so already-joined pairs cost one compare.
+__global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ seg,
+                                                const int32_t *__restrict__ tile_off, int nseg,
+                                                const int32_t *__restrict__ notstar,
+                                                int32_t *__restrict__ parent, DevParams p, double h,
+                                                uint64_t *stats, uint64_t *fam)
+{
+    __shared__ double jx[TPB], jy[TPB], jz[TPB], jvx[TPB], jvy[TPB], jvz[TPB], jm[TPB];
+    __shared__ int32_t jroot[TPB];
+    __shared__ uint64_t sh[4];
+    const int s = find_seg(tile_off, nseg, blockIdx.x);
+    if (!notstar[s]) return;
+    const Seg g = seg[s];
+    const int T = (g.n + TPB - 1) / TPB;
+    int t = blockIdx.x - tile_off[s];
+    int ti = 0;
+    while (t >= T - ti) {
+        t -= T - ti;
+        ti++;
+    }
+    const int tj = ti + t;
+    const int jbase = g.start + tj * TPB;
+    const int jn = min(TPB, g.n - tj * TPB);
+    if (threadIdx.x < jn) {
+        const int j = jbase + threadIdx.x;
+        jx[threadIdx.x] = S.x[j];
+        jy[threadIdx.x] = S.y[j];
+        jz[threadIdx.x] = S.z[j];
+        jvx[threadIdx.x] = S.vx[j];
+        jvy[threadIdx.x] = S.vy[j];
+        jvz[threadIdx.x] = S.vz[j];
+        jm[threadIdx.x] = S.m[j];
+        jroot[threadIdx.x] = gfind(parent, j);
+    }
+    __syncthreads();
+    const int il = ti * TPB + threadIdx.x;
+    uint64_t ev = 0;
+    if (il < g.n) {
+        const int i = g.start + il;
+        const double xi = S.x[i], yi = S.y[i], zi = S.z[i];
+        const double vxi = S.vx[i], vyi = S.vy[i], vzi = S.vz[i], mi = S.m[i];
+        int32_t ri = gfind(parent, i);
+        const int j0 = (ti == tj) ? threadIdx.x + 1 : 0;
+        ev = (jn > j0) ? (uint64_t)(jn - j0) : 0;
+        for (int jj = j0; jj < jn; ++jj) {
+            if (edge_pair(xi - jx[jj], yi - jy[jj], zi - jz[jj], vxi - jvx[jj], vyi - jvy[jj], vzi - jvz[jj],
+                          mi + jm[jj], p, h)) {
+                const int32_t rj = jroot[jj];
+                if (rj != ri) {
+                    ri = gunite(parent, ri, rj);
+                    jroot[jj] = ri;
+                }
+            }
+        }
+    }
+    const uint64_t tot = block_sum_u64(ev, sh);
+    if (threadIdx.x == 0) {
+        stat_add(stats, g.cluster, ST_TAU, tot);
+        fam_add(fam, 0, tot);
+    }
+}
+
+// Labels (smallest slot of the component) and component sizes.
+__global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, const int32_t *__restrict__ chunk_off,
+                                                int nseg, const int32_t *__restrict__ notstar,
+                                                int32_t *__restrict__ parent, int32_t *__restrict__ label,
+                                                int32_t *__restrict__ cnt, uint64_t *stats)
+{
+    const int s = find_seg(chunk_off, nseg, blockIdx.x);
+    const Seg g = seg[s];
+    const int local = (blockIdx.x - chunk_off[s]) * TPB + threadIdx.x;
+    const bool ns = notstar[s] != 0;
+    if (local < g.n) {
+        const int u = g.start + local;
+        const int32_t l = ns ? gfind(parent, u) : g.start;
+        label[u] = l;
+        atomicAdd(&cnt[l], 1);
+    }
+    if (local == 0) {
+        const uint64_t n = (uint64_t)g.n;
+        stat_add(stats, g.cluster, ST_TAU_ALG, ns ? n * (n - 1) / 2 : n - 1);
+        stat_add(stats, g.cluster, ST_SPLIT, 1);
+        stat_max(stats, g.cluster, g.depth);
+    }
+}
+
+// Sort keys: active index k -> slot; key = label (ascending label groups a
+// component, stable sort keeps members in slot order).
+__global__ void k_keys(const Seg *__restrict__ seg, const int32_t *__restrict__ act_off, int nseg, int nact,
+                       const int32_t *__restrict__ label, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
+{
+    const int k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= nact) return;
+    const int s = find_seg(act_off, nseg, k);
+    const int slot = seg[s].start + (k - act_off[s]);
+    keys[k] = (uint32_t)label[slot];
+    vals[k] = (uint32_t)slot;
+}
+
+struct Tmp {
+    double *x, *y, *z, *vx, *vy, *vz, *m;
+    int32_t *orig, *lab;
+};
+
+// T[k] = W[from[k]] (from == NULL: from = act(k)); optionally the entry
+// label of the moved particle and the entry-order singleton flag.
+__global__ void k_gather(SoA W, Tmp T, const Seg *__restrict__ seg, const int32_t *__restrict__ act_off,
+                         int nseg, int nact, const uint32_t *__restrict__ from, const int32_t *__restrict__ label,
+                         const int32_t *__restrict__ cnt, uint8_t *__restrict__ sing)
+{
+    const int k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= nact) return;
+    int src;
+    if (from) {
+        src = (int)from[k];
+    } else {
+        const int s = find_seg(act_off, nseg, k);
+        src = seg[s].start + (k - act_off[s]);
+    }
+    T.x[k] = W.x[src];
+    T.y[k] = W.y[src];
+    T.z[k] = W.z[src];
+    T.vx[k] = W.vx[src];
+    T.vy[k] = W.vy[src];
+    T.vz[k] = W.vz[src];
+    T.m[k] = W.m[src];
+    T.orig[k] = W.orig[src];
+    if (label) {
+        const int32_t l = label[src];
+        T.lab[k] = l;
+        sing[src] = (cnt[l] == 1) ? 1 : 0;
+    }
+}
+
+// W[to[k]] = T[k] (to == NULL: to = act(k)).  With `lists`, also classify the
+// components now contiguous in slot order: pairs, small (binned by size) and
+// big components are appended to the level's work lists.
+struct Lists {
+    Seg *pairs;
+    Seg *small[4];
+    Seg *big;
+    int32_t *count;  // [0] pairs, [1..4] small bins, [5] big
+    int32_t cap_pairs, cap_small, cap_big;
+    int32_t small_max;
+    int32_t bin_lim[3];  // upper sizes of bins 0..2 (bin 3 up to small_max)
+    int32_t *labp;       // optional: label of the particle now at each slot
+    uint8_t *singp;      // optional: singleton flag of the particle now at each slot
+};
+
+__global__ void k_scatter(SoA W, Tmp T, const Seg *__restrict__ seg, const int32_t *__restrict__ act_off,
+                          int nseg, int nact, const uint32_t *__restrict__ to, const int32_t *__restrict__ cnt,
+                          Lists L, int with_lists, uint64_t *stats)
+{
+    const int k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= nact) return;
+    int dst;
+    int s = 0;
+    if (to) {
+        dst = (int)to[k];
+    } else {
+        s = find_seg(act_off, nseg, k);
+        dst = seg[s].start + (k - act_off[s]);
+    }
+    W.x[dst] = T.x[k];
+    W.y[dst] = T.y[k];
+    W.z[dst] = T.z[k];
+    W.vx[dst] = T.vx[k];
+    W.vy[dst] = T.vy[k];
+    W.vz[dst] = T.vz[k];
+    W.m[dst] = T.m[k];
+    W.orig[dst] = T.orig[k];
+    if (!with_lists) return;
+    const int32_t l = T.lab[k];
+    if (L.labp) {
+        L.labp[dst] = l;
+        L.singp[dst] = (cnt[l] == 1) ? 1 : 0;
+    }
+    const bool first = (k == act_off[s]) || (T.lab[k - 1] != l);
+    if (!first) return;
+    const int32_t size = cnt[l];
+    if (size < 2) return;
+    const Seg g = seg[s];
+    stat_add(stats, g.cluster, ST_COMP, 1);
+    const Seg c = {dst, size, g.cluster, g.depth + 1};
+    if (size == 2) {
+        const int i = atomicAdd(&L.count[0], 1);
+        if (i < L.cap_pairs) L.pairs[i] = c;
+    } else if (size <= L.small_max) {
+        const int b = size <= L.bin_lim[0] ? 0 : size <= L.bin_lim[1] ? 1 : size <= L.bin_lim[2] ? 2 : 3;
+        const int i = atomicAdd(&L.count[1 + b], 1);
+        if (i < L.cap_small) L.small[b][i] = c;
+    } else {
+        const int i = atomicAdd(&L.count[5], 1);
+        if (i < L.cap_big) L.big[i] = c;
+    }
+}
+
+// Drift D_{hh} of the segment's singletons (entry order).
+__global__ void k_drift_seg(SoA W, const Seg *__restrict__ seg, const int32_t *__restrict__ chunk_off, int nseg,
+                            const uint8_t *__restrict__ sing, double hh, uint64_t *stats)
+{
+    __shared__ uint64_t sh[4];
+    const int s = find_seg(chunk_off, nseg, blockIdx.x);
+    const Seg g = seg[s];
+    const int local = (blockIdx.x - chunk_off[s]) * TPB + threadIdx.x;
+    uint64_t c = 0;
+    if (local < g.n) {
+        const int u = g.start + local;
+        if (sing[u]) {
+            W.x[u] += hh * W.vx[u];
+            W.y[u] += hh * W.vy[u];
+            W.z[u] += hh * W.vz[u];
+            c = 1;
+        }
+    }
+    const uint64_t t = block_sum_u64(c, sh);
+    if (threadIdx.x == 0) stat_add(stats, g.cluster, ST_DRIFT, t);
+}
+
+// Kick K_h for all pairs of a segment with different labels (V_R + V_CC +
+// V_CR, eq. 30).  Each particle sums its partners in ascending slot order
+// (= ascending particle index within the segment), exactly the order in
+// which a sequential i<j sweep accumulates both members of every pair.
+// label == NULL kicks every pair.
+__global__ __launch_bounds__(TPB) void k_kick_seg(SoA W, const Seg *__restrict__ seg,
+                                                   const int32_t *__restrict__ chunk_off, int nseg,
+                                                   const int32_t *__restrict__ label, double h, double eps2,
+                                                   double G, int32_t *err, uint64_t *stats, uint64_t *fam)
+{
+    __shared__ double jx[TPB], jy[TPB], jz[TPB], jm[TPB];
+    __shared__ int32_t jl[TPB];
+    __shared__ uint64_t sh[4];
+    const int s = find_seg(chunk_off, nseg, blockIdx.x);
+    const Seg g = seg[s];
+    const int local = (blockIdx.x - chunk_off[s]) * TPB + threadIdx.x;
+    const bool valid = local < g.n;
+    const int i = g.start + (valid ? local : 0);
+    const double xi = W.x[i], yi = W.y[i], zi = W.z[i];
+    const int32_t li = label ? label[i] : i;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    uint64_t pairs = 0;
+    bool ok = true;
+    for (int jb = 0; jb < g.n; jb += TPB) {
+        const int jn = min(TPB, g.n - jb);
+        __syncthreads();
+        if (threadIdx.x < jn) {
+            const int j = g.start + jb + threadIdx.x;
+            jx[threadIdx.x] = W.x[j];
+            jy[threadIdx.x] = W.y[j];
+            jz[threadIdx.x] = W.z[j];
+            jm[threadIdx.x] = W.m[j];
+            jl[threadIdx.x] = label ? label[j] : j;
+        }
+        __syncthreads();
+        if (valid) {
+            for (int jj = 0; jj < jn; ++jj) {
+                const int j = g.start + jb + jj;
+                if (jl[jj] == li || j == i) continue;
+                ok &= accel_term(xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, G, ax, ay, az);
+                pairs += (j > i);
+            }
+        }
+    }
+    if (valid) {
+        if (!ok) atomicOr(err, EB_NONFINITE);
+        W.vx[i] += h * ax;
+        W.vy[i] += h * ay;
+        W.vz[i] += h * az;
+    }
+    const uint64_t t = block_sum_u64(pairs, sh);
+    if (threadIdx.x == 0 && stats) {
+        stat_add(stats, g.cluster, ST_KICK, t);
+        fam_add(fam, 1, t);
+    }
+}
+
+// Kick K_h in the component-contiguous slot order (labels non-decreasing
+// within a segment).  Block b covers one 256-particle i tile and one group of
+// j tiles of its segment; a j tile lying inside the i tile's own component is
+// skipped whole (all its pairs are inside one component).  Each block writes
+// its partial accelerations; k_kick_combine adds the groups of every i in
+// group order, so the result is deterministic.
+__global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict__ seg,
+                                                     const int32_t *__restrict__ kick_off,
+                                                     const int32_t *__restrict__ kgrp, int nseg,
+                                                     const int32_t *__restrict__ labp, double eps2, double G,
+                                                     double *__restrict__ part, int32_t *err, uint64_t *stats,
+                                                     uint64_t *fam)
+{
+    __shared__ double jx[TPB], jy[TPB], jz[TPB], jm[TPB];
+    __shared__ int32_t jl[TPB];
+    __shared__ uint64_t sh[4];
+    const int s = find_seg(kick_off, nseg, blockIdx.x);
+    const Seg g = seg[s];
+    const int T = (g.n + TPB - 1) / TPB;
+    const int Gs = kgrp[s];
+    const int local = blockIdx.x - kick_off[s];
+    const int I = local / Gs, grp = local % Gs;
+    const int per = (T + Gs - 1) / Gs;
+    const int t0 = grp * per, t1 = min(T, t0 + per);
+    const int il = I * TPB + threadIdx.x;
+    const bool valid = il < g.n;
+    const int i = g.start + (valid ? il : 0);
+    const double xi = W.x[i], yi = W.y[i], zi = W.z[i];
+    const int32_t li = labp[i];
+    const int ifirst = g.start + I * TPB, ilast = g.start + min(g.n, (I + 1) * TPB) - 1;
+    const int32_t iu = (labp[ifirst] == labp[ilast]) ? labp[ifirst] : -1;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    uint64_t pairs = 0;
+    bool ok = true;
+    for (int t = t0; t < t1; ++t) {
+        const int jb = t * TPB;
+        const int jn = min(TPB, g.n - jb);
+        const int jfirst = g.start + jb, jlast = g.start + jb + jn - 1;
+        if (iu >= 0 && labp[jfirst] == iu && labp[jlast] == iu) continue;  // uniform across the block
+        __syncthreads();
+        if (threadIdx.x < jn) {
+            const int j = g.start + jb + threadIdx.x;
+            jx[threadIdx.x] = W.x[j];
+            jy[threadIdx.x] = W.y[j];
+            jz[threadIdx.x] = W.z[j];
+            jm[threadIdx.x] = W.m[j];
+            jl[threadIdx.x] = labp[j];
+        }
+        __syncthreads();
+        if (valid) {
+            for (int jj = 0; jj < jn; ++jj) {
+                if (jl[jj] == li) continue;
+                ok &= accel_term(xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, G, ax, ay, az);
+                pairs += (jb + jj > il);
+            }
+        }
+    }
+    double *pb = part + (size_t)blockIdx.x * 3 * TPB;
+    pb[threadIdx.x] = ax;
+    pb[TPB + threadIdx.x] = ay;
+    pb[2 * TPB + threadIdx.x] = az;
+    if (valid && !ok) atomicOr(err, EB_NONFINITE);
+    const uint64_t tot = block_sum_u64(pairs, sh);
+    if (threadIdx.x == 0) {
+        stat_add(stats, g.cluster, ST_KICK, tot);
+        fam_add(fam, 1, tot);
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_kick_combine(SoA W, const Seg *__restrict__ seg,
+                                                       const int32_t *__restrict__ chunk_off,
+                                                       const int32_t *__restrict__ kick_off,
+                                                       const int32_t *__restrict__ kgrp, int nseg,
+                                                       const double *__restrict__ part, double h)
+{
+    const int s = find_seg(chunk_off, nseg, blockIdx.x);
+    const Seg g = seg[s];
+    const int I = blockIdx.x - chunk_off[s];
+    const int il = I * TPB + threadIdx.x;
+    if (il >= g.n) return;
+    const int Gs = kgrp[s];
+    const double *pb = part + (size_t)(kick_off[s] + I * Gs) * 3 * TPB;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    for (int q = 0; q < Gs; ++q) {
+        ax += pb[(size_t)q * 3 * TPB + threadIdx.x];
+        ay += pb[(size_t)q * 3 * TPB + TPB + threadIdx.x];
+        az += pb[(size_t)q * 3 * TPB + 2 * TPB + threadIdx.x];
+    }
+    const int u = g.start + il;
+    W.vx[u] += h * ax;
+    W.vy[u] += h * ay;
+    W.vz[u] += h * az;
+}
+
+// Kick used by the cc_kick entry point: same sums, but velocities are written
+// to separate output arrays so that a failing call leaves the state untouched.
+__global__ __launch_bounds__(TPB) void k_kick_all(SoA W, int n, const int32_t *__restrict__ label, double eps2,
+                                                   double G, double *__restrict__ ax_out,
+                                                   double *__restrict__ ay_out, double *__restrict__ az_out,
+                                                   int32_t *err)
+{
+    __shared__ double jx[TPB], jy[TPB], jz[TPB], jm[TPB];
+    __shared__ int32_t jl[TPB];
+    const int i0 = blockIdx.x * TPB + threadIdx.x;
+    const bool valid = i0 < n;
+    const int i = valid ? i0 : 0;
+    const double xi = W.x[i], yi = W.y[i], zi = W.z[i];
+    const int32_t li = label ? label[i] : i;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    bool ok = true;
+    for (int jb = 0; jb < n; jb += TPB) {
+        const int jn = min(TPB, n - jb);
+        __syncthreads();
+        if (threadIdx.x < jn) {
+            const int j = jb + threadIdx.x;
+            jx[threadIdx.x] = W.x[j];
+            jy[threadIdx.x] = W.y[j];
+            jz[threadIdx.x] = W.z[j];
+            jm[threadIdx.x] = W.m[j];
+            jl[threadIdx.x] = label ? label[j] : j;
+        }
+        __syncthreads();
+        if (valid) {
+            for (int jj = 0; jj < jn; ++jj) {
+                const int j = jb + jj;
+                if (jl[jj] == li || j == i) continue;
+                ok &= accel_term(xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, G, ax, ay, az);
+            }
+        }
+    }
+    if (valid) {
+        if (!ok) atomicOr(err, EB_NONFINITE);
+        ax_out[i] = ax;
+        ay_out[i] = ay;
+        az_out[i] = az;
+    }
+}
+
+__global__ void k_apply_kick(SoA W, int n, const double *__restrict__ ax, const double *__restrict__ ay,
+                             const double *__restrict__ az, double h)
+{
+    const int i = blockIdx.x * TPB + threadIdx.x;
+    if (i >= n) return;
+    W.vx[i] += h * ax[i];
+    W.vy[i] += h * ay[i];
+    W.vz[i] += h * az[i];
+}
+
+// ---------------------------------------------------------------------------
+// Two-particle components, one per lane.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(TPB) void k_pairs(SoA W, const Seg *__restrict__ items, const int32_t *__restrict__ count,
+                                                int cap, double H, DevParams p, int32_t *err, uint64_t *stats,
+                                                uint64_t *fam)
+{
+    const int n = min(count[0], cap);
+    for (int it = blockIdx.x * TPB + threadIdx.x; it < n; it += gridDim.x * TPB) {
+        const Seg g = items[it];
+        int ia = g.start, ib = g.start + 1;
+        if (W.orig[ib] < W.orig[ia]) {
+            ia = g.start + 1;
+            ib = g.start;
+        }
+        Body a{W.x[ia], W.y[ia], W.z[ia], W.vx[ia], W.vy[ia], W.vz[ia], W.m[ia]};
+        Body b{W.x[ib], W.y[ib], W.z[ib], W.vx[ib], W.vy[ib], W.vz[ib], W.m[ib]};
+        PairCounters c{0, 0, 0, 0, 0, -1};
+        const int e = evolve_pair(a, b, H, g.depth, p, c);
+        if (e) atomicOr(err, e);
+        W.x[ia] = a.x; W.y[ia] = a.y; W.z[ia] = a.z; W.vx[ia] = a.vx; W.vy[ia] = a.vy; W.vz[ia] = a.vz;
+        W.x[ib] = b.x; W.y[ib] = b.y; W.z[ib] = b.z; W.vx[ib] = b.vx; W.vy[ib] = b.vy; W.vz[ib] = b.vz;
+        stat_add(stats, g.cluster, ST_TAU, c.tau);
+        stat_add(stats, g.cluster, ST_TAU_ALG, c.tau);
+        stat_add(stats, g.cluster, ST_KICK, c.kick);
+        stat_add(stats, g.cluster, ST_DRIFT, c.drift);
+        stat_add(stats, g.cluster, ST_COMP, c.comp);
+        stat_add(stats, g.cluster, ST_SPLIT, c.split);
+        if (c.maxd >= 0) stat_max(stats, g.cluster, c.maxd);
+        fam_add(fam, 0, c.tau);
+        fam_add(fam, 1, c.kick);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// On-chip recursion for one component per workgroup (3 <= n <= CAP).
+//
+// The state lives in LDS.  The recursion of Fig. 2 is walked level by level:
+// level k holds the list L_k of sets to evolve with h_k = H / 2^k (level 0 is
+// the item itself).  Splitting L_k reorders each set so that its components
+// are contiguous, and records two bitmasks per level: component starts (cs)
+// and membership of a non-trivial component (nt); the non-trivial components
+// form L_{k+1}.  Sets of two particles are handed to one lane each and run
+// to completion (evolve_pair).  Independent sets of one level are processed
+// together, which is exact because they share no particles.
+// ---------------------------------------------------------------------------
+constexpr int MAXL = 64;
+
+template <int CAP>
+struct SmallLDS {
+    double x[CAP], y[CAP], z[CAP], vx[CAP], vy[CAP], vz[CAP], m[CAP];
+    int32_t orig[CAP];
+    int32_t par[CAP];
+    int32_t cnt[CAP];
+    int16_t entry[CAP];
+    int16_t segS[CAP];
+    int16_t segE[CAP];
+    int16_t aux[CAP];
+    int16_t cid[CAP];
+    uint32_t cs[MAXL][CAP / 32];
+    uint32_t nt[MAXL][CAP / 32];
+    uint32_t flag[CAP / 32];
+    int16_t binlist[CAP / 2];
+    uint8_t phase[MAXL];
+    uint8_t hasnt[MAXL];
+    int32_t wsum[4];
+    unsigned long long ctr[8];
+    int32_t nbin;
+    int32_t item;
+    int32_t err;
+    int32_t maxd;
+};
+
+__device__ __forceinline__ bool bit_of(const uint32_t *w, int p) { return (w[p >> 5] >> (p & 31)) & 1u; }
+
+__device__ __forceinline__ int32_t lload(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int32_t lfind(int32_t *par, int32_t a)
+{
+    for (int it = 0; it < FIND_BUDGET; ++it) {
+        const int32_t q = lload(&par[a]);
+        if (q == a) return a;
+        a = q;
+    }
+    return a;
+}
+
+__device__ __forceinline__ void lunite(int32_t *par, int32_t a, int32_t b)
+{
+    for (int it = 0; it < FIND_BUDGET; ++it) {
+        a = lfind(par, a);
+        b = lfind(par, b);
+        if (a == b) return;
+        if (a > b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(&par[b], b, a) == b) return;
+    }
+}
+
+template <int CAP, bool EXACT>
+struct SmallKernel {
+    static constexpr int E = CAP / TPB;  // positions per thread
+    static constexpr int W = CAP / 32;   // mask words
+
+    // Mask word of level-k segment starts: L_k = non-trivial components of level k-1.
+    static __device__ __forceinline__ uint32_t start_word(const SmallLDS<CAP> &L, int k, int wi, int n)
+    {
+        if (k == 0) return wi == 0 ? 1u : 0u;
+        return L.cs[k - 1][wi] & L.nt[k - 1][wi];
+    }
+
+    static __device__ __forceinline__ uint32_t end_word(const SmallLDS<CAP> &L, int k, int wi, int n)
+    {
+        uint32_t w;
+        if (k == 0) w = (wi == 0) ? 1u : 0u;
+        else w = (L.cs[k - 1][wi] & L.nt[k - 1][wi]) | ~L.nt[k - 1][wi];
+        // positions >= n end every segment
+        const int lo = wi * 32;
+        if (lo + 32 > n) {
+            const int keep = n - lo;  // bits below keep are real positions
+            const uint32_t beyond = keep <= 0 ? 0xFFFFFFFFu : (keep >= 32 ? 0u : (0xFFFFFFFFu << keep));
+            w |= beyond;
+        }
+        return w;
+    }
+
+    // segS/segE for every position of L_k (-1 outside) and the list of
+    // two-particle sets.
+    static __device__ void enumerate(SmallLDS<CAP> &L, int k, int n, bool collect_bins)
+    {
+        if (threadIdx.x == 0) L.nbin = 0;
+        __syncthreads();
+        for (int p = threadIdx.x; p < n; p += TPB) {
+            const bool inL = (k == 0) || bit_of(L.nt[k - 1], p);
+            if (!inL) {
+                L.segS[p] = -1;
+                continue;
+            }
+            // previous start
+            int wi = p >> 5;
+            uint32_t bits = start_word(L, k, wi, n) & (0xFFFFFFFFu >> (31 - (p & 31)));
+            while (!bits && wi > 0) bits = start_word(L, k, --wi, n);
+            const int s = bits ? wi * 32 + 31 - __clz(bits) : 0;
+            // next end strictly after p (a segment start, a position outside L_k, or n)
+            int e = n;
+            wi = p >> 5;
+            const int sh = (p & 31) + 1;
+            bits = sh < 32 ? (end_word(L, k, wi, n) & (0xFFFFFFFFu << sh)) : 0u;
+            for (;;) {
+                if (bits) {
+                    e = min(n, wi * 32 + __ffs(bits) - 1);
+                    break;
+                }
+                if (++wi * 32 >= n) break;
+                bits = end_word(L, k, wi, n);
+            }
+            L.segS[p] = (int16_t)s;
+            L.segE[p] = (int16_t)e;
+            if (collect_bins && p == s && e - s == 2) {
+                const int i = atomicAdd(&L.nbin, 1);
+                L.binlist[i] = (int16_t)s;
+            }
+        }
+        __syncthreads();
+    }
+
+    static __device__ void count(SmallLDS<CAP> &L, int idx, unsigned long long v)
+    {
+        if (v) atomicAdd(&L.ctr[idx], v);
+    }
+
+    static __device__ void run_binaries(SmallLDS<CAP> &L, double h, int depth, const DevParams &p)
+    {
+        const int nb = L.nbin;
+        PairCounters c{0, 0, 0, 0, 0, -1};
+        for (int i = threadIdx.x; i < nb; i += TPB) {
+            int ia = L.binlist[i], ib = ia + 1;
+            if (L.orig[ib] < L.orig[ia]) {
+                const int t = ia;
+                ia = ib;
+                ib = t;
+            }
+            Body a{L.x[ia], L.y[ia], L.z[ia], L.vx[ia], L.vy[ia], L.vz[ia], L.m[ia]};
+            Body b{L.x[ib], L.y[ib], L.z[ib], L.vx[ib], L.vy[ib], L.vz[ib], L.m[ib]};
+            const int e = evolve_pair(a, b, h, depth, p, c);
+            if (e) atomicOr(&L.err, e);
+            L.x[ia] = a.x; L.y[ia] = a.y; L.z[ia] = a.z; L.vx[ia] = a.vx; L.vy[ia] = a.vy; L.vz[ia] = a.vz;
+            L.x[ib] = b.x; L.y[ib] = b.y; L.z[ib] = b.z; L.vx[ib] = b.vx; L.vy[ib] = b.vy; L.vz[ib] = b.vz;
+        }
+        count(L, ST_TAU, c.tau);
+        count(L, ST_TAU_ALG, c.tau);
+        count(L, ST_KICK, c.kick);
+        count(L, ST_DRIFT, c.drift);
+        count(L, ST_COMP, c.comp);
+        count(L, ST_SPLIT, c.split);
+        if (c.maxd >= 0) atomicMax(&L.maxd, c.maxd);
+        __syncthreads();
+    }
+
+    // Exclusive prefix sum of cnt[0..CAP) into par[].
+    static __device__ void scan_cnt(SmallLDS<CAP> &L)
+    {
+        int v[E];
+        int tot = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            v[e] = L.cnt[threadIdx.x * E + e];
+            tot += v[e];
+        }
+        int incl = tot;
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) L.wsum[w] = incl;
+        __syncthreads();
+        int before = incl - tot;
+        for (int q = 0; q < w; ++q) before += L.wsum[q];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            L.par[threadIdx.x * E + e] = before;
+            before += v[e];
+        }
+        __syncthreads();
+    }
+
+    static __device__ __forceinline__ bool is_main(const SmallLDS<CAP> &L, int p)
+    {
+        const int s = L.segS[p];
+        return s >= 0 && (L.segE[p] - s) >= 3;
+    }
+
+    // Split every main set of L_k at h (eq. 20) and reorder it by component.
+    static __device__ void split(SmallLDS<CAP> &L, int k, int n, double h, const DevParams &p)
+    {
+        for (int w = threadIdx.x; w < W; w += TPB) {
+            L.flag[w] = 0;
+            L.cs[k][w] = 0;
+            L.nt[k][w] = 0;
+        }
+        for (int q = threadIdx.x; q < CAP; q += TPB) L.cnt[q] = 0;
+        __syncthreads();
+        unsigned long long tau = 0;
+        // star test from each set's first position X
+        for (int q = threadIdx.x; q < n; q += TPB) {
+            if (!is_main(L, q)) continue;
+            L.par[q] = q;
+            const int X = L.segS[q];
+            if (q == X) continue;
+            tau++;
+            if (!edge_pair(L.x[X] - L.x[q], L.y[X] - L.y[q], L.z[X] - L.z[q], L.vx[X] - L.vx[q],
+                           L.vy[X] - L.vy[q], L.vz[X] - L.vz[q], L.m[X] + L.m[q], p, h))
+                atomicOr(&L.flag[X >> 5], 1u << (X & 31));
+        }
+        __syncthreads();
+        // all-pairs sweep of the sets that are not stars
+        for (int a = threadIdx.x; a < n; a += TPB) {
+            if (!is_main(L, a)) continue;
+            const int s = L.segS[a];
+            if (!bit_of(L.flag, s)) continue;
+            const int e = L.segE[a];
+            const double xa = L.x[a], ya = L.y[a], za = L.z[a], vxa = L.vx[a], vya = L.vy[a], vza = L.vz[a],
+                         ma = L.m[a];
+            for (int b = a + 1; b < e; ++b) {
+                if (edge_pair(xa - L.x[b], ya - L.y[b], za - L.z[b], vxa - L.vx[b], vya - L.vy[b],
+                              vza - L.vz[b], ma + L.m[b], p, h))
+                    lunite(L.par, a, b);
+            }
+            tau += (unsigned long long)(e - a - 1);
+        }
+        count(L, ST_TAU, tau);
+        __syncthreads();
+        // labels and sizes
+        for (int a = threadIdx.x; a < n; a += TPB) {
+            if (!is_main(L, a)) continue;
+            const int s = L.segS[a];
+            const int lab = bit_of(L.flag, s) ? lfind(L.par, a) : s;
+            L.cid[a] = (int16_t)lab;
+            atomicAdd(&L.cnt[lab], 1);
+        }
+        __syncthreads();
+        scan_cnt(L);
+        // destination of every position: components in label order, members
+        // in position order
+        int dst[E], rk[E], sz[E];
+        unsigned long long comps = 0, splits = 0, alg = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int a = threadIdx.x + e * TPB;
+            dst[e] = -1;
+            if (a >= n || !is_main(L, a)) continue;
+            const int s = L.segS[a];
+            const int lab = L.cid[a];
+            int r = 0;
+            for (int q = lab; q < a; ++q) r += (L.cid[q] == lab);
+            const int size = L.cnt[lab];
+            dst[e] = s + (L.par[lab] - L.par[s]) + r;
+            rk[e] = r;
+            sz[e] = size;
+            if (a == lab && size >= 2) comps++;
+            if (a == s) {
+                const unsigned long long m = (unsigned long long)(L.segE[a] - s);
+                splits++;
+                alg += bit_of(L.flag, s) ? m * (m - 1) / 2 : m - 1;
+            }
+        }
+        count(L, ST_COMP, comps);
+        count(L, ST_SPLIT, splits);
+        count(L, ST_TAU_ALG, alg);
+        // move
+        double rx[E], ry[E], rz[E], rvx[E], rvy[E], rvz[E], rm[E];
+        int32_t ro[E];
+        int16_t re[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int a = threadIdx.x + e * TPB;
+            if (dst[e] < 0) continue;
+            rx[e] = L.x[a]; ry[e] = L.y[a]; rz[e] = L.z[a];
+            rvx[e] = L.vx[a]; rvy[e] = L.vy[a]; rvz[e] = L.vz[a]; rm[e] = L.m[a];
+            ro[e] = L.orig[a];
+            re[e] = L.entry[a];
+        }
+        __syncthreads();
+        bool any_nt = false;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int d = dst[e];
+            if (d < 0) continue;
+            L.x[d] = rx[e]; L.y[d] = ry[e]; L.z[d] = rz[e];
+            L.vx[d] = rvx[e]; L.vy[d] = rvy[e]; L.vz[d] = rvz[e]; L.m[d] = rm[e];
+            L.orig[d] = ro[e];
+            L.entry[d] = re[e];
+            if (rk[e] == 0) atomicOr(&L.cs[k][d >> 5], 1u << (d & 31));
+            if (sz[e] >= 2) {
+                atomicOr(&L.nt[k][d >> 5], 1u << (d & 31));
+                any_nt = true;
+            }
+        }
+        if (threadIdx.x == 0) L.hasnt[k] = 0;
+        __syncthreads();
+        if (any_nt) L.hasnt[k] = 1;
+        __syncthreads();
+    }
+
+    // Drift R by h/2, kick every pair of a main set in different components by
+    // h, drift R by h/2 (eq. 30).  Partners are summed in ascending original
+    // index, the order of a sequential i<j sweep over the set.
+    static __device__ void kick_drift(SoA /*unused*/, SmallLDS<CAP> &L, int k, int n, double h,
+                                      const DevParams &p)
+    {
+        const double hh = 0.5 * h;
+        unsigned long long drifts = 0, kicks = 0;
+        bool ok = true;
+        for (int a = threadIdx.x; a < n; a += TPB) {
+            if (!is_main(L, a)) continue;
+            int wi = a >> 5;
+            uint32_t bits = L.cs[k][wi] & (0xFFFFFFFFu >> (31 - (a & 31)));
+            while (!bits && wi > 0) bits = L.cs[k][--wi];
+            L.cid[a] = (int16_t)(bits ? wi * 32 + 31 - __clz(bits) : L.segS[a]);
+            if (!bit_of(L.nt[k], a)) {
+                L.x[a] += hh * L.vx[a];
+                L.y[a] += hh * L.vy[a];
+                L.z[a] += hh * L.vz[a];
+                drifts++;
+            }
+        }
+        __syncthreads();
+        // Partner order: with EXACT, ascending original index (the order of a
+        // sequential i<j sweep over the set); otherwise slot order.
+        for (int a = threadIdx.x; a < n; a += TPB) {
+            if (!is_main(L, a)) continue;
+            const int s = L.segS[a], e = L.segE[a];
+            bool multi = false;
+            for (int q = s + 1; q < e && !multi; ++q) multi = bit_of(L.cs[k], q);
+            if (!multi) {
+                L.aux[a] = -1;
+                continue;
+            }
+            if (EXACT) {
+                const int oa = L.orig[a];
+                int r = 0;
+                for (int q = s; q < e; ++q) r += (L.orig[q] < oa);
+                L.aux[s + r] = (int16_t)a;
+            } else {
+                L.aux[a] = (int16_t)a;
+            }
+        }
+        __syncthreads();
+        for (int a = threadIdx.x; a < n; a += TPB) {
+            if (!is_main(L, a)) continue;
+            const int s = L.segS[a], e = L.segE[a];
+            if (L.aux[s] < 0) continue;  // a single component: nothing to kick
+            const double xa = L.x[a], ya = L.y[a], za = L.z[a];
+            const int ca = L.cid[a];
+            const int oa = L.orig[a];
+            double ax = 0.0, ay = 0.0, az = 0.0;
+            for (int t = s; t < e; ++t) {
+                const int q = EXACT ? L.aux[t] : t;
+                if (L.cid[q] == ca) continue;
+                ok &= accel_term(xa, ya, za, L.x[q], L.y[q], L.z[q], L.m[q], p.eps2, p.G, ax, ay, az);
+                kicks += (L.orig[q] > oa);
+            }
+            // velocities are not read by the kick, so each thread updates its own
+            L.vx[a] += h * ax;
+            L.vy[a] += h * ay;
+            L.vz[a] += h * az;
+        }
+        if (!ok) atomicOr(&L.err, EB_NONFINITE);
+        __syncthreads();
+        for (int a = threadIdx.x; a < n; a += TPB) {
+            if (!is_main(L, a)) continue;
+            if (!bit_of(L.nt[k], a)) {
+                L.x[a] += hh * L.vx[a];
+                L.y[a] += hh * L.vy[a];
+                L.z[a] += hh * L.vz[a];
+                drifts++;
+            }
+        }
+        count(L, ST_DRIFT, drifts);
+        count(L, ST_KICK, kicks);
+        __syncthreads();
+    }
+
+    static __device__ void run_item(SoA Wg, SmallLDS<CAP> &L, const Seg g, double H, const DevParams &p,
+                                    int32_t *err, uint64_t *stats, uint64_t *fam)
+    {
+        const int n = g.n;
+        for (int a = threadIdx.x; a < n; a += TPB) {
+            const int u = g.start + a;
+            L.x[a] = Wg.x[u]; L.y[a] = Wg.y[u]; L.z[a] = Wg.z[u];
+            L.vx[a] = Wg.vx[u]; L.vy[a] = Wg.vy[u]; L.vz[a] = Wg.vz[u]; L.m[a] = Wg.m[u];
+            L.orig[a] = Wg.orig[u];
+            L.entry[a] = (int16_t)a;
+        }
+        if (threadIdx.x < 8) L.ctr[threadIdx.x] = 0;
+        if (threadIdx.x == 0) {
+            L.err = 0;
+            L.maxd = -1;
+            L.phase[0] = 0;
+        }
+        __syncthreads();
+        int k = 0;
+        double h = H;
+        uint64_t visits = 0;
+        for (;;) {
+            if (++visits > ITEM_VISIT_BUDGET) {
+                if (threadIdx.x == 0) L.err |= EB_BUDGET;
+                __syncthreads();
+                break;
+            }
+            int ph = L.phase[k];
+            bool descend = false;
+            bool fresh = false;
+            if (ph == 0) {
+                const int depth = g.depth + k;
+                if (depth > p.max_depth || k >= MAXL - 1) {
+                    if (threadIdx.x == 0) L.err |= EB_DEPTH;
+                    __syncthreads();
+                    break;
+                }
+                if (threadIdx.x == 0) atomicMax(&L.maxd, depth);
+                enumerate(L, k, n, true);
+                run_binaries(L, h, depth, p);
+                if (L.err) break;
+                split(L, k, n, h, p);
+                if (L.hasnt[k]) {
+                    descend = true;
+                    if (threadIdx.x == 0) L.phase[k] = 1;
+                } else {
+                    ph = 1;
+                    fresh = true;
+                }
+            }
+            if (!descend && ph == 1) {
+                if (!fresh) enumerate(L, k, n, false);
+                kick_drift(Wg, L, k, n, h, p);
+                if (L.err) break;
+                if (L.hasnt[k]) {
+                    descend = true;
+                    if (threadIdx.x == 0) L.phase[k] = 2;
+                }
+            }
+            if (descend) {
+                if (threadIdx.x == 0) L.phase[k + 1] = 0;
+                __syncthreads();
+                k++;
+                h = 0.5 * h;
+                continue;
+            }
+            // level k finished (both halves, or no components)
+            __syncthreads();
+            if (k == 0) break;
+            k--;
+            h = 2.0 * h;
+        }
+        __syncthreads();
+        if (L.err) {
+            if (threadIdx.x == 0) atomicOr(err, L.err);
+        } else {
+            for (int a = threadIdx.x; a < n; a += TPB) {
+                const int u = g.start + L.entry[a];
+                Wg.x[u] = L.x[a]; Wg.y[u] = L.y[a]; Wg.z[u] = L.z[a];
+                Wg.vx[u] = L.vx[a]; Wg.vy[u] = L.vy[a]; Wg.vz[u] = L.vz[a];
+            }
+        }
+        if (threadIdx.x < 7 && threadIdx.x != ST_MAXD) stat_add(stats, g.cluster, threadIdx.x, L.ctr[threadIdx.x]);
+        if (threadIdx.x == 0) {
+            fam_add(fam, 0, L.ctr[ST_TAU]);
+            fam_add(fam, 1, L.ctr[ST_KICK]);
+        }
+        if (threadIdx.x == 0 && L.maxd >= 0) stat_max(stats, g.cluster, L.maxd);
+        __syncthreads();
+    }
+};
+
+struct SmallItems {
+    const Seg *bin[4];
+    const int32_t *count;  // counts of bins 0..3 at count[0..3]
+    int32_t cap;
+};
+
+template <int CAP, bool EXACT>
+__global__ __launch_bounds__(TPB) void k_small(SoA W, SmallItems items, int32_t *qhead, double H, DevParams p,
+                                                int32_t *err, uint64_t *stats, uint64_t *fam)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    SmallLDS<CAP> &L = *reinterpret_cast<SmallLDS<CAP> *>(smem_raw);
+    int c[4];
+    for (int b = 0; b < 4; ++b) c[b] = min(items.count[b], items.cap);
+    const int total = c[0] + c[1] + c[2] + c[3];
+    for (;;) {
+        if (threadIdx.x == 0) L.item = atomicAdd(qhead, 1);
+        __syncthreads();
+        int it = L.item;
+        __syncthreads();
+        if (it >= total) break;
+        // largest sizes first
+        int b = 3;
+        while (it >= c[b]) {
+            it -= c[b];
+            b--;
+        }
+        const Seg g = items.bin[b][it];
+        if (g.n == 1) {
+            // a lone particle: split gives R = {it}; drift h/2 twice
+            if (threadIdx.x == 0) {
+                const int u = g.start;
+                const double hh = 0.5 * H;
+                for (int r = 0; r < 2; ++r) {
+                    W.x[u] += hh * W.vx[u];
+                    W.y[u] += hh * W.vy[u];
+                    W.z[u] += hh * W.vz[u];
+                }
+                stat_add(stats, g.cluster, ST_DRIFT, 2);
+                stat_add(stats, g.cluster, ST_SPLIT, 1);
+                stat_max(stats, g.cluster, g.depth);
+            }
+            continue;
+        }
+        SmallKernel<CAP, EXACT>::run_item(W, L, g, H, p, err, stats, fam);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Diagnostics: per-block Neumaier partials, combined in a fixed order.
+// ---------------------------------------------------------------------------
+struct NS {
+    double s, c;
+};
+
+__device__ __forceinline__ void ns_add(NS &a, double v)
+{
+    const double t = a.s + v;
+    if (fabs(a.s) >= fabs(v)) a.c += (a.s - t) + v;
+    else a.c += (v - t) + a.s;
+    a.s = t;
+}
+
+__device__ __forceinline__ void ns_merge(NS &a, const NS &b)
+{
+    ns_add(a, b.s);
+    ns_add(a, b.c);
+}
+
+constexpr int NDIAG = 12;
+
+__global__ __launch_bounds__(TPB) void k_diag(SoA S, int n, double eps2, double G, double *__restrict__ part)
+{
+    __shared__ double jx[TPB], jy[TPB], jz[TPB], jm[TPB];
+    __shared__ NS red[TPB];
+    const int i0 = blockIdx.x * TPB + threadIdx.x;
+    const bool valid = i0 < n;
+    const int i = valid ? i0 : 0;
+    NS acc[NDIAG];
+    for (int q = 0; q < NDIAG; ++q) acc[q] = NS{0.0, 0.0};
+    const double xi = S.x[i], yi = S.y[i], zi = S.z[i], mi = S.m[i];
+    if (valid) {
+        const double vx = S.vx[i], vy = S.vy[i], vz = S.vz[i];
+        const double v2 = (vx * vx + vy * vy) + vz * vz;
+        ns_add(acc[0], 0.5 * mi * v2);
+        ns_add(acc[2], mi * vx); ns_add(acc[3], mi * vy); ns_add(acc[4], mi * vz);
+        ns_add(acc[5], mi * (yi * vz - zi * vy));
+        ns_add(acc[6], mi * (zi * vx - xi * vz));
+        ns_add(acc[7], mi * (xi * vy - yi * vx));
+        ns_add(acc[8], mi * xi); ns_add(acc[9], mi * yi); ns_add(acc[10], mi * zi);
+        ns_add(acc[11], mi);
+    }
+    const int jstart = blockIdx.x * TPB;  // pairs j > i only
+    for (int jb = jstart; jb < n; jb += TPB) {
+        const int jn = min(TPB, n - jb);
+        __syncthreads();
+        if (threadIdx.x < jn) {
+            jx[threadIdx.x] = S.x[jb + threadIdx.x];
+            jy[threadIdx.x] = S.y[jb + threadIdx.x];
+            jz[threadIdx.x] = S.z[jb + threadIdx.x];
+            jm[threadIdx.x] = S.m[jb + threadIdx.x];
+        }
+        __syncthreads();
+        if (valid) {
+            for (int jj = 0; jj < jn; ++jj) {
+                if (jb + jj <= i) continue;
+                const double dx = jx[jj] - xi, dy = jy[jj] - yi, dz = jz[jj] - zi;
+                const double r2 = ((dx * dx + dy * dy) + dz * dz) + eps2;
+                ns_add(acc[1], -G * mi * jm[jj] / sqrt(r2));
+            }
+        }
+    }
+    // block reduction in fixed (tree) order, one quantity at a time
+    for (int q = 0; q < NDIAG; ++q) {
+        __syncthreads();
+        red[threadIdx.x] = acc[q];
+        __syncthreads();
+        for (int st = TPB / 2; st > 0; st >>= 1) {
+            if (threadIdx.x < st) ns_merge(red[threadIdx.x], red[threadIdx.x + st]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            part[(size_t)blockIdx.x * NDIAG * 2 + 2 * q] = red[0].s;
+            part[(size_t)blockIdx.x * NDIAG * 2 + 2 * q + 1] = red[0].c;
+        }
+    }
+}
+
+__global__ void k_diag_final(const double *__restrict__ part, int nblk, double *__restrict__ out)
+{
+    const int q = threadIdx.x;
+    if (q >= NDIAG) return;
+    NS a{0.0, 0.0};
+    for (int b = 0; b < nblk; ++b) {
+        ns_add(a, part[(size_t)b * NDIAG * 2 + 2 * q]);
+        ns_add(a, part[(size_t)b * NDIAG * 2 + 2 * q + 1]);
+    }
+    out[q] = a.s + a.c;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (declared in cc_launch.h)
+// ---------------------------------------------------------------------------
+static inline int nblocks(int64_t n, int cap = 65535 * 16)
+{
+    int64_t b = (n + TPB - 1) / TPB;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+hipError_t launch_validate(const double *x, const double *y, const double *z, const double *vx, const double *vy,
+                           const double *vz, const double *m, int64_t n, int32_t *err, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_validate, dim3(nblocks(n, 4096)), dim3(TPB), 0, st, x, y, z, vx, vy, vz, m, n, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_tau(SoA S, const int32_t *pi, const int32_t *pj, int64_t npairs, double *out, DevParams p,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pair_tau, dim3(nblocks(npairs, 8192)), dim3(TPB), 0, st, S, pi, pj, npairs, out, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_drift_mask(SoA S, int64_t n, const uint8_t *mask, double h, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_drift_mask, dim3(nblocks(n, 4096)), dim3(TPB), 0, st, S, n, mask, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t *a, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_iota, dim3(nblocks(n, 4096)), dim3(TPB), 0, st, a, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(n, 4096)), dim3(TPB), 0, st, a, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, int32_t *cnt, DevParams p,
+                       double h, uint64_t *stats, uint64_t *fam, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_star, dim3(a.nchunks), dim3(TPB), 0, st, S, a.seg, a.chunk_off, a.nseg, notstar, parent, cnt,
+                       p, h, stats, fam);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, DevParams p, double h,
+                        uint64_t *stats, uint64_t *fam, hipStream_t st)
+{
+    if (a.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sweep, dim3(a.ntiles), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar, parent, p,
+                       h, stats, fam);
+    return hipGetLastError();
+}
+
+hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,
+                        uint64_t *stats, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_label, dim3(a.nchunks), dim3(TPB), 0, st, a.seg, a.chunk_off, a.nseg, notstar, parent, label,
+                       cnt, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_keys(const GridLevelArgs &a, const int32_t *label, uint32_t *keys, uint32_t *vals, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_keys, dim3(nblocks(a.nact, 1 << 30)), dim3(TPB), 0, st, a.seg, a.act_off, a.nseg, a.nact,
+                       label, keys, vals);
+    return hipGetLastError();
+}
+
+size_t sort_temp_bytes(int n)
+{
+    size_t bytes = 0;
+    (void)rocprim::radix_sort_pairs(nullptr, bytes, (uint32_t *)nullptr, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                              (uint32_t *)nullptr, (size_t)n, 0, 32, 0, false);
+    return bytes;
+}
+
+hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, uint32_t *keys_out,
+                       const uint32_t *vals_in, uint32_t *vals_out, int n, int end_bit, hipStream_t st)
+{
+    size_t need = 0;
+    hipError_t e = rocprim::radix_sort_pairs(nullptr, need, keys_in, keys_out, vals_in, vals_out, (size_t)n, 0,
+                                             end_bit, st, false);
+    if (e != hipSuccess) return e;
+    if (need > temp_bytes) return hipErrorInvalidValue;
+    size_t bytes = temp_bytes;
+    return rocprim::radix_sort_pairs(temp, bytes, keys_in, keys_out, vals_in, vals_out, (size_t)n, 0, end_bit, st,
+                                     false);
+}
+
+hipError_t launch_permute(SoA W, const TmpArrays &t, const GridLevelArgs &a, const uint32_t *src,
+                          const int32_t *label, const int32_t *cnt, uint8_t *sing, const ListArgs *lists,
+                          uint64_t *stats, bool inverse, hipStream_t st)
+{
+    Tmp T{t.x, t.y, t.z, t.vx, t.vy, t.vz, t.m, t.orig, t.lab};
+    const int nb = nblocks(a.nact, 1 << 30);
+    if (!inverse) {
+        hipLaunchKernelGGL(k_gather, dim3(nb), dim3(TPB), 0, st, W, T, a.seg, a.act_off, a.nseg, a.nact, src, label,
+                           cnt, sing);
+        Lists L{};
+        int with = 0;
+        if (lists) {
+            with = 1;
+            L.pairs = lists->pairs;
+            for (int b = 0; b < 4; ++b) L.small[b] = lists->small[b];
+            L.big = lists->big;
+            L.count = lists->count;
+            L.cap_pairs = lists->cap_pairs;
+            L.cap_small = lists->cap_small;
+            L.cap_big = lists->cap_big;
+            L.small_max = lists->small_max;
+            for (int b = 0; b < 3; ++b) L.bin_lim[b] = lists->bin_lim[b];
+            L.labp = lists->labp;
+            L.singp = lists->singp;
+        }
+        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(TPB), 0, st, W, T, a.seg, a.act_off, a.nseg, a.nact,
+                           (const uint32_t *)nullptr, cnt, L, with, stats);
+    } else {
+        hipLaunchKernelGGL(k_gather, dim3(nb), dim3(TPB), 0, st, W, T, a.seg, a.act_off, a.nseg, a.nact,
+                           (const uint32_t *)nullptr, (const int32_t *)nullptr, (const int32_t *)nullptr,
+                           (uint8_t *)nullptr);
+        Lists L{};
+        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(TPB), 0, st, W, T, a.seg, a.act_off, a.nseg, a.nact, src, cnt, L,
+                           0, stats);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_drift_seg(SoA W, const GridLevelArgs &a, const uint8_t *sing, double hh, uint64_t *stats,
+                            hipStream_t st)
+{
+    hipLaunchKernelGGL(k_drift_seg, dim3(a.nchunks), dim3(TPB), 0, st, W, a.seg, a.chunk_off, a.nseg, sing, hh,
+                       stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, double h, double eps2, double G,
+                           int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_kick_seg, dim3(a.nchunks), dim3(TPB), 0, st, W, a.seg, a.chunk_off, a.nseg, label, h, eps2,
+                       G, err, stats, fam);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const int32_t *labp, double h, double eps2, double G,
+                             double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_kick_tiles, dim3(a.nkblocks), dim3(TPB), 0, st, W, a.seg, a.kick_off, a.kgrp, a.nseg, labp,
+                       eps2, G, part, err, stats, fam);
+    hipLaunchKernelGGL(k_kick_combine, dim3(a.nchunks), dim3(TPB), 0, st, W, a.seg, a.chunk_off, a.kick_off, a.kgrp,
+                       a.nseg, (const double *)part, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, double *ax, double *ay,
+                           double *az, int32_t *err, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_kick_all, dim3(nblocks(n, 1 << 30)), dim3(TPB), 0, st, W, n, label, eps2, G, ax, ay, az, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, const double *az, double h,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_apply_kick, dim3(nblocks(n, 1 << 30)), dim3(TPB), 0, st, W, n, ax, ay, az, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs(SoA W, const Seg *items, const int32_t *count, int cap, int nitems, double H, DevParams p,
+                        int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pairs, dim3(nblocks(nitems, 4096)), dim3(TPB), 0, st, W, items, count, cap, H, p, err,
+                       stats, fam);
+    return hipGetLastError();
+}
+
+template <int CAP, bool EXACT>
+static hipError_t launch_small_cap(SoA W, const SmallArgs &s, double H, DevParams p, int32_t *err, uint64_t *stats,
+                                   uint64_t *fam, int nblk, hipStream_t st)
+{
+    static bool configured = false;
+    const size_t lds = sizeof(SmallLDS<CAP>);
+    if (!configured) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_small<CAP, EXACT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        configured = true;
+    }
+    SmallItems it{};
+    for (int b = 0; b < 4; ++b) it.bin[b] = s.bin[b];
+    it.count = s.count;
+    it.cap = s.cap;
+    hipLaunchKernelGGL((k_small<CAP, EXACT>), dim3(nblk), dim3(TPB), lds, st, W, it, s.qhead, H, p, err, stats, fam);
+    return hipGetLastError();
+}
+
+size_t small_lds_bytes(int cap)
+{
+    if (cap <= 256) return sizeof(SmallLDS<256>);
+    if (cap <= 512) return sizeof(SmallLDS<512>);
+    return sizeof(SmallLDS<1024>);
+}
+
+hipError_t launch_small(SoA W, const SmallArgs &s, int cap, bool exact, double H, DevParams p, int32_t *err,
+                        uint64_t *stats, uint64_t *fam, int nblk, hipStream_t st)
+{
+    if (nblk <= 0) return hipSuccess;
+    if (exact) {
+        if (cap <= 256) return launch_small_cap<256, true>(W, s, H, p, err, stats, fam, nblk, st);
+        if (cap <= 512) return launch_small_cap<512, true>(W, s, H, p, err, stats, fam, nblk, st);
+        return launch_small_cap<1024, true>(W, s, H, p, err, stats, fam, nblk, st);
+    }
+    if (cap <= 256) return launch_small_cap<256, false>(W, s, H, p, err, stats, fam, nblk, st);
+    if (cap <= 512) return launch_small_cap<512, false>(W, s, H, p, err, stats, fam, nblk, st);
+    return launch_small_cap<1024, false>(W, s, H, p, err, stats, fam, nblk, st);
+}
+
+int diag_blocks(int n) { return nblocks(n, 1 << 30); }
+
+hipError_t launch_diag(SoA S, int n, double eps2, double G, double *part, double *out, hipStream_t st)
+{
+    const int nb = diag_blocks(n);
+    hipLaunchKernelGGL(k_diag, dim3(nb), dim3(TPB), 0, st, S, n, eps2, G, part);
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, part, nb, out);
+    return hipGetLastError();
+}
+
+}  // namespace ccg

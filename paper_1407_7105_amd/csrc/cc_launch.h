@@ -1,0 +1,89 @@
+// cc_launch.h -- host-side launchers of the kernels in cc_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "cc_device.h"
+
+namespace ccg {
+
+// Segment list of one grid level, already on the device.
+struct GridLevelArgs {
+    const Seg *seg;
+    const int32_t *chunk_off;  // prefix over ceil(n/256) slot chunks, nseg+1
+    const int32_t *tile_off;   // prefix over triangular 256x256 tiles (non-star sweep), nseg+1
+    const int32_t *act_off;    // prefix over n, nseg+1
+    const int32_t *kick_off;   // prefix over kick blocks (i tiles x j groups), nseg+1
+    const int32_t *kgrp;       // j groups per segment, nseg
+    int nseg, nchunks, ntiles, nact, nkblocks;
+};
+
+struct TmpArrays {
+    double *x, *y, *z, *vx, *vy, *vz, *m;
+    int32_t *orig, *lab;
+};
+
+struct ListArgs {
+    Seg *pairs;
+    Seg *small[4];
+    Seg *big;
+    int32_t *count;  // [0] pairs, [1..4] small bins, [5] big
+    int32_t cap_pairs, cap_small, cap_big;
+    int32_t small_max;
+    int32_t bin_lim[3];
+    int32_t *labp;   // optional permuted-order labels
+    uint8_t *singp;  // optional permuted-order singleton flags
+};
+
+struct SmallArgs {
+    const Seg *bin[4];
+    const int32_t *count;  // 4 bin counts
+    int32_t cap;
+    int32_t *qhead;
+};
+
+hipError_t launch_validate(const double *x, const double *y, const double *z, const double *vx, const double *vy,
+                           const double *vz, const double *m, int64_t n, int32_t *err, hipStream_t st);
+hipError_t launch_pair_tau(SoA S, const int32_t *pi, const int32_t *pj, int64_t npairs, double *out, DevParams p,
+                           hipStream_t st);
+hipError_t launch_drift_mask(SoA S, int64_t n, const uint8_t *mask, double h, hipStream_t st);
+hipError_t launch_iota(int32_t *a, int64_t n, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t st);
+
+hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, int32_t *cnt, DevParams p,
+                       double h, uint64_t *stats, uint64_t *fam, hipStream_t st);
+hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, DevParams p, double h,
+                        uint64_t *stats, uint64_t *fam, hipStream_t st);
+hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,
+                        uint64_t *stats, hipStream_t st);
+hipError_t launch_keys(const GridLevelArgs &a, const int32_t *label, uint32_t *keys, uint32_t *vals, hipStream_t st);
+size_t sort_temp_bytes(int n);
+hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, uint32_t *keys_out,
+                       const uint32_t *vals_in, uint32_t *vals_out, int n, int end_bit, hipStream_t st);
+// forward (inverse == false): W[act(k)] <- W[src[k]]; with `label`, also the
+// entry-order singleton flags, and with `lists` the component work lists.
+// inverse: W[src[k]] <- W[act(k)].
+hipError_t launch_permute(SoA W, const TmpArrays &t, const GridLevelArgs &a, const uint32_t *src,
+                          const int32_t *label, const int32_t *cnt, uint8_t *sing, const ListArgs *lists,
+                          uint64_t *stats, bool inverse, hipStream_t st);
+hipError_t launch_drift_seg(SoA W, const GridLevelArgs &a, const uint8_t *sing, double hh, uint64_t *stats,
+                            hipStream_t st);
+hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, double h, double eps2, double G,
+                           int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
+hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const int32_t *labp, double h, double eps2, double G,
+                             double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
+hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, double *ax, double *ay,
+                           double *az, int32_t *err, hipStream_t st);
+hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, const double *az, double h,
+                             hipStream_t st);
+hipError_t launch_pairs(SoA W, const Seg *items, const int32_t *count, int cap, int nitems, double H, DevParams p,
+                        int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
+size_t small_lds_bytes(int cap);
+hipError_t launch_small(SoA W, const SmallArgs &s, int cap, bool exact, double H, DevParams p, int32_t *err,
+                        uint64_t *stats, uint64_t *fam, int nblk, hipStream_t st);
+int diag_blocks(int n);
+hipError_t launch_diag(SoA S, int n, double eps2, double G, double *part, double *out, hipStream_t st);
+
+}  // namespace ccg
