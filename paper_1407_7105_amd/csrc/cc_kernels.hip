@@ -108,6 +108,39 @@ __device__ __forceinline__ int32_t gunite(int32_t *par, int32_t a, int32_t b)
     return a;
 }
 
+// LDS union-find (same rule: the smaller root becomes the parent)
+__device__ __forceinline__ bool bit_of(const uint32_t *w, int p) { return (w[p >> 5] >> (p & 31)) & 1u; }
+
+__device__ __forceinline__ int32_t lload(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int32_t lfind(int32_t *par, int32_t a)
+{
+    for (int it = 0; it < FIND_BUDGET; ++it) {
+        const int32_t q = lload(&par[a]);
+        if (q == a) return a;
+        a = q;
+    }
+    return a;
+}
+
+__device__ __forceinline__ void lunite(int32_t *par, int32_t a, int32_t b)
+{
+    for (int it = 0; it < FIND_BUDGET; ++it) {
+        a = lfind(par, a);
+        b = lfind(par, b);
+        if (a == b) return;
+        if (a > b) {
+            const int32_t t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(&par[b], b, a) == b) return;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Elementwise kernels
 // ---------------------------------------------------------------------------
@@ -197,8 +230,12 @@ __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg
 
 // All-pairs sweep of a segment that failed the star test: for each pair
 // i<j with tau(i,j) < h, merge their sets.  One block per (i-tile, j-tile)
-// with i-tile <= j-tile; the j tile is staged in LDS together with each j's
-// set root at load time, so already-joined pairs cost one compare.
+// with i-tile <= j-tile.  Edges are first joined in a union-find local to the
+// block, in LDS, over the tile's 512 particles (256 when i-tile = j-tile);
+// each particle's global root is read once at tile start and an edge between
+// particles that already share it is skipped.  Afterwards every particle whose
+// local set root has a different global root is merged globally -- at most
+// one global union per particle per tile instead of one per edge.
 __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ seg,
                                                 const int32_t *__restrict__ tile_off, int nseg,
                                                 const int32_t *__restrict__ notstar,
@@ -206,7 +243,8 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
                                                 uint64_t *stats, uint64_t *fam)
 {
     __shared__ double jx[TPB], jy[TPB], jz[TPB], jvx[TPB], jvy[TPB], jvz[TPB], jm[TPB];
-    __shared__ int32_t jroot[TPB];
+    __shared__ int32_t lpar[2 * TPB];
+    __shared__ int32_t groot[2 * TPB];
     __shared__ uint64_t sh[4];
     const int s = find_seg(tile_off, nseg, blockIdx.x);
     if (!notstar[s]) return;
@@ -219,8 +257,16 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
         ti++;
     }
     const int tj = ti + t;
+    const bool diag = (ti == tj);
     const int jbase = g.start + tj * TPB;
     const int jn = min(TPB, g.n - tj * TPB);
+    const int il = ti * TPB + threadIdx.x;
+    const bool ivalid = il < g.n;
+    const int i = g.start + (ivalid ? il : 0);
+    lpar[threadIdx.x] = threadIdx.x;
+    lpar[TPB + threadIdx.x] = TPB + threadIdx.x;
+    groot[threadIdx.x] = ivalid ? gfind(parent, i) : -1;
+    groot[TPB + threadIdx.x] = -1;
     if (threadIdx.x < jn) {
         const int j = jbase + threadIdx.x;
         jx[threadIdx.x] = S.x[j];
@@ -230,28 +276,32 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
         jvy[threadIdx.x] = S.vy[j];
         jvz[threadIdx.x] = S.vz[j];
         jm[threadIdx.x] = S.m[j];
-        jroot[threadIdx.x] = gfind(parent, j);
+        if (!diag) groot[TPB + threadIdx.x] = gfind(parent, j);
     }
     __syncthreads();
-    const int il = ti * TPB + threadIdx.x;
     uint64_t ev = 0;
-    if (il < g.n) {
-        const int i = g.start + il;
+    if (ivalid) {
         const double xi = S.x[i], yi = S.y[i], zi = S.z[i];
         const double vxi = S.vx[i], vyi = S.vy[i], vzi = S.vz[i], mi = S.m[i];
-        int32_t ri = gfind(parent, i);
-        const int j0 = (ti == tj) ? threadIdx.x + 1 : 0;
+        const int vi = threadIdx.x;
+        const int32_t gi = groot[vi];
+        const int j0 = diag ? threadIdx.x + 1 : 0;
+        const int joff = diag ? 0 : TPB;
         ev = (jn > j0) ? (uint64_t)(jn - j0) : 0;
         for (int jj = j0; jj < jn; ++jj) {
             if (edge_pair(xi - jx[jj], yi - jy[jj], zi - jz[jj], vxi - jvx[jj], vyi - jvy[jj], vzi - jvz[jj],
                           mi + jm[jj], p, h)) {
-                const int32_t rj = jroot[jj];
-                if (rj != ri) {
-                    ri = gunite(parent, ri, rj);
-                    jroot[jj] = ri;
-                }
+                const int vj = joff + jj;
+                if (groot[vj] != gi) lunite(lpar, vi, vj);
             }
         }
+    }
+    __syncthreads();
+    // merge the block's local sets into the global structure
+    for (int v = threadIdx.x; v < 2 * TPB; v += TPB) {
+        if (groot[v] < 0) continue;
+        const int r = lfind(lpar, v);
+        if (r != v && groot[r] != groot[v]) gunite(parent, groot[v], groot[r]);
     }
     const uint64_t tot = block_sum_u64(ev, sh);
     if (threadIdx.x == 0) {
@@ -694,38 +744,6 @@ struct SmallLDS {
     int32_t err;
     int32_t maxd;
 };
-
-__device__ __forceinline__ bool bit_of(const uint32_t *w, int p) { return (w[p >> 5] >> (p & 31)) & 1u; }
-
-__device__ __forceinline__ int32_t lload(const int32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-__device__ __forceinline__ int32_t lfind(int32_t *par, int32_t a)
-{
-    for (int it = 0; it < FIND_BUDGET; ++it) {
-        const int32_t q = lload(&par[a]);
-        if (q == a) return a;
-        a = q;
-    }
-    return a;
-}
-
-__device__ __forceinline__ void lunite(int32_t *par, int32_t a, int32_t b)
-{
-    for (int it = 0; it < FIND_BUDGET; ++it) {
-        a = lfind(par, a);
-        b = lfind(par, b);
-        if (a == b) return;
-        if (a > b) {
-            const int32_t t = a;
-            a = b;
-            b = t;
-        }
-        if (atomicCAS(&par[b], b, a) == b) return;
-    }
-}
 
 template <int CAP, bool EXACT>
 struct SmallKernel {
