@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -32,6 +33,8 @@ namespace {
 
 constexpr int TPB = 256;
 constexpr int DEFAULT_SMALL_MAX = 256;
+constexpr int kLevels = 64;  // grid recursion levels a context can hold (max_depth <= 60)
+constexpr int SWEEP_TILE = 64;  // edge of the all-pairs sweep tiles
 
 // kernel families for timing
 enum Fam { F_STAR, F_SWEEP, F_LABEL, F_SORT, F_PERMUTE, F_DRIFT, F_KICK, F_PAIRS, F_SMALL, F_VALIDATE, F_OTHER, F_N };
@@ -78,6 +81,9 @@ struct cc_ctx {
     cc_params params{};
     std::string err;
     hipStream_t st = nullptr;
+    hipStream_t side = nullptr;            // second stream: small/pair components overlap the grid recursion
+    std::vector<hipEvent_t> sync_pool;     // ordering events (no timing)
+    std::vector<hipEvent_t> sync_used;
     int cus = 256;
     size_t cap = 0;
     size_t cap_cl = 0;
@@ -150,6 +156,11 @@ DevParams dev_params(const cc_ctx *c)
 }
 
 int small_max(const cc_ctx *c) { return c->params.small_max > 0 ? c->params.small_max : DEFAULT_SMALL_MAX; }
+
+bool mixed(const cc_ctx *c) { return c->params.precision == CC_MIXED; }
+
+// The mixed path sums kicks over parallel tiles; EXACT order applies to FP64.
+bool exact_order(const cc_ctx *c) { return !mixed(c) && c->params.kick_order == CC_ORDER_EXACT; }
 
 int check_params(cc_ctx *c, const cc_params *p)
 {
@@ -286,12 +297,13 @@ hipEvent_t get_event(cc_ctx *c)
 struct Span {
     cc_ctx *c;
     int fam;
+    hipStream_t s;
     hipEvent_t a = nullptr;
-    Span(cc_ctx *cc, int f) : c(cc), fam(f)
+    Span(cc_ctx *cc, int f, hipStream_t stream = nullptr) : c(cc), fam(f), s(stream ? stream : cc->st)
     {
         if (c->timing) {
             a = get_event(c);
-            if (a) hipEventRecord(a, c->st);
+            if (a) hipEventRecord(a, s);
         }
     }
     ~Span()
@@ -299,17 +311,41 @@ struct Span {
         if (c->timing && a) {
             hipEvent_t b = get_event(c);
             if (b) {
-                hipEventRecord(b, c->st);
+                hipEventRecord(b, s);
                 c->recs.push_back({fam, a, b});
             }
         }
     }
 };
 
+// An ordering event recorded on `from`; `to` waits for it.
+int order_streams(cc_ctx *c, hipStream_t from, hipStream_t to)
+{
+    hipEvent_t e;
+    if (!c->sync_pool.empty()) {
+        e = c->sync_pool.back();
+        c->sync_pool.pop_back();
+    } else {
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    c->sync_used.push_back(e);
+    HIPCHK(hipEventRecord(e, from));
+    HIPCHK(hipStreamWaitEvent(to, e, 0));
+    return CC_OK;
+}
+
+// after a full synchronisation of both streams the ordering events are free again
+void recycle_sync_events(cc_ctx *c)
+{
+    for (auto e : c->sync_used) c->sync_pool.push_back(e);
+    c->sync_used.clear();
+}
+
 void flush_timing(cc_ctx *c)
 {
     if (c->recs.empty()) return;
     hipStreamSynchronize(c->st);
+    hipStreamSynchronize(c->side);
     for (auto &r : c->recs) {
         float ms = 0.f;
         hipEventElapsedTime(&ms, r.a, r.b);
@@ -343,29 +379,31 @@ int err_code(cc_ctx *c, int bits)
     return CC_OK;
 }
 
-int run_small_and_pairs(cc_ctx *c, Level &lv, double H, int n_pairs, int n_small)
+// Work-queue heads are per level: the on-chip kernel of a level may still run
+// on the side stream while a deeper level launches its own on the main stream.
+int run_small_and_pairs(cc_ctx *c, int k, Level &lv, double H, int n_pairs, int n_small, hipStream_t st)
 {
     const DevParams p = dev_params(c);
     SoA W = work_soa(c);
     if (n_pairs > 0) {
-        Span s(c, F_PAIRS);
-        HIPCHK(launch_pairs(W, lv.pairs, lv.count, lv.cap_pairs, n_pairs, H, p, c->errf, c->stats, fam_ptr(c, F_PAIRS),
-                            c->st));
+        Span s(c, F_PAIRS, st);
+        HIPCHK(launch_pairs(W, lv.pairs, lv.count, lv.cap_pairs, n_pairs, H, p, mixed(c), c->errf, c->stats,
+                            fam_ptr(c, F_PAIRS), st));
     }
     if (n_small > 0) {
-        HIPCHK(launch_fill_i32(c->qhead, 1, 0, c->st));
+        HIPCHK(launch_fill_i32(c->qhead + k, 1, 0, st));
         SmallArgs sa{};
         for (int b = 0; b < 4; ++b) sa.bin[b] = lv.small[b];
         sa.count = lv.count + 1;
         sa.cap = lv.cap_small;
-        sa.qhead = c->qhead;
+        sa.qhead = c->qhead + k;
         const int sm = small_max(c);
         const size_t lds = small_lds_bytes(sm);
         int per_cu = (int)std::min<size_t>(8, std::max<size_t>(1, (160 * 1024) / (lds + 1024)));
         const int nblk = std::min(n_small, c->cus * per_cu);
-        Span s(c, F_SMALL);
-        HIPCHK(launch_small(W, sa, sm, c->params.kick_order == CC_ORDER_EXACT, H, p, c->errf, c->stats,
-                            fam_ptr(c, F_SMALL), nblk, c->st));
+        Span s(c, F_SMALL, st);
+        HIPCHK(launch_small(W, sa, sm, mixed(c) ? 2 : (exact_order(c) ? 1 : 0), H, p, c->errf, c->stats,
+                            fam_ptr(c, F_SMALL), nblk, st));
     }
     return CC_OK;
 }
@@ -373,11 +411,40 @@ int run_small_and_pairs(cc_ctx *c, Level &lv, double H, int n_pairs, int n_small
 int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h);
 
 // Items of one list of independent sets at level depth: route by size.
+// The small and two-particle components of a level and its large components
+// are disjoint sets: the former run on the side stream while the host drives
+// the recursion into the latter on the main stream; the main stream waits for
+// the side stream before the level's own kick.
 int dispatch_sets(cc_ctx *c, int k, Level &lv, double H, const std::vector<Seg> &big, int n_pairs, int n_small)
 {
-    RC(run_small_and_pairs(c, lv, H, n_pairs, n_small));
-    if (!big.empty()) RC(evolve_grid(c, k + 1, big, H));
+    if (big.empty() || n_pairs + n_small == 0) {
+        RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, c->st));
+        if (!big.empty()) RC(evolve_grid(c, k + 1, big, H));
+        return CC_OK;
+    }
+    RC(order_streams(c, c->st, c->side));
+    RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, c->side));
+    hipEvent_t done;
+    if (!c->sync_pool.empty()) {
+        done = c->sync_pool.back();
+        c->sync_pool.pop_back();
+    } else {
+        HIPCHK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    }
+    c->sync_used.push_back(done);
+    HIPCHK(hipEventRecord(done, c->side));
+    RC(evolve_grid(c, k + 1, big, H));
+    HIPCHK(hipStreamWaitEvent(c->st, done, 0));
     return CC_OK;
+}
+
+bool trace_on()
+{
+    static const int on = [] {
+        const char *e = std::getenv("CC_TRACE");
+        return (e && *e && *e != '0') ? 1 : 0;
+    }();
+    return on != 0;
 }
 
 int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
@@ -405,7 +472,8 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         const int n = segs[s].n;
         const int64_t T = (n + TPB - 1) / TPB;
         const int64_t G = std::min<int64_t>(T, gtarget);
-        const int64_t nt = tile[s] + T * (T + 1) / 2, nk = koff[s] + T * G;
+        const int64_t T64 = (n + SWEEP_TILE - 1) / SWEEP_TILE;
+        const int64_t nt = tile[s] + T64 * (T64 + 1) / 2, nk = koff[s] + T * G;
         if (nt > INT32_MAX || nk > INT32_MAX) return fail(c, CC_ERR_ARG, "set of %d particles is too large", n);
         chunk[s + 1] = chunk[s] + (int32_t)T;
         tile[s + 1] = (int32_t)nt;
@@ -417,7 +485,7 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     HIPCHK(hipMemcpyAsync(lv.offs, lv.h_offs, 5 * S1 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
     GridLevelArgs a{lv.seg, lv.offs, lv.offs + S1, lv.offs + 2 * S1, lv.offs + 3 * S1, lv.offs + 4 * S1,
                     nseg, chunk[nseg], tile[nseg], act[nseg], koff[nseg]};
-    const bool exact = c->params.kick_order == CC_ORDER_EXACT;
+    const bool exact = exact_order(c);
     if (!exact && (size_t)a.nkblocks > c->kick_part_cap) {
         RC(dalloc(c, &c->kick_part, (size_t)a.nkblocks * 3 * TPB));
         c->kick_part_cap = a.nkblocks;
@@ -426,11 +494,11 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     HIPCHK(launch_fill_i32(lv.count, 8, 0, c->st));
     {
         Span s(c, F_STAR);
-        HIPCHK(launch_star(W, a, lv.notstar, c->parent, c->cnt, p, h, c->stats, fam_ptr(c, F_STAR), c->st));
+        HIPCHK(launch_star(W, a, lv.notstar, c->parent, c->cnt, p, h, mixed(c), c->stats, fam_ptr(c, F_STAR), c->st));
     }
     {
         Span s(c, F_SWEEP);
-        HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, c->stats, fam_ptr(c, F_SWEEP), c->st));
+        HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, mixed(c), c->stats, fam_ptr(c, F_SWEEP), c->st));
     }
     {
         Span s(c, F_LABEL);
@@ -481,6 +549,12 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     std::sort(big.begin(), big.end(), [](const Seg &x, const Seg &y) { return x.start < y.start; });
     const bool any_sub = (n_pairs + n_small + n_big) > 0;
     const double H = 0.5 * h;
+    if (trace_on()) {
+        int nmax = 0;
+        for (const Seg &g : segs) nmax = std::max(nmax, g.n);
+        std::fprintf(stderr, "cc-trace level=%d nseg=%d nact=%d nmax=%d pairs=%d small=%d/%d/%d/%d big=%d\n", k, nseg,
+                     a.nact, nmax, n_pairs, lv.h_count[1], lv.h_count[2], lv.h_count[3], lv.h_count[4], n_big);
+    }
 
     if (!exact) {
         // Component-contiguous order throughout: first half, drift/kick/drift
@@ -493,8 +567,8 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         }
         {
             Span s(c, F_KICK);
-            HIPCHK(launch_kick_tiles(W, a, lv2.labp, h, c->params.eps2, c->params.G, c->kick_part, c->errf, c->stats,
-                                     fam_ptr(c, F_KICK), c->st));
+            HIPCHK(launch_kick_tiles(W, a, lv2.labp, h, c->params.eps2, c->params.G, mixed(c), c->kick_part, c->errf,
+                                     c->stats, fam_ptr(c, F_KICK), c->st));
         }
         {
             Span s(c, F_DRIFT);
@@ -579,7 +653,7 @@ int global_step(cc_ctx *c, const std::vector<Seg> &top, double dt)
                 HIPCHK(hipMemcpyAsync(lv.small[b], small[b].data(), small[b].size() * sizeof(Seg),
                                       hipMemcpyHostToDevice, c->st));
         const int ns = (int)(small[0].size() + small[1].size() + small[2].size() + small[3].size());
-        RC(run_small_and_pairs(c, lv, dt, (int)pairs.size(), ns));
+        RC(run_small_and_pairs(c, k, lv, dt, (int)pairs.size(), ns, c->st));
         // the host vectors must outlive the async copies
         HIPCHK(hipStreamSynchronize(c->st));
     }
@@ -649,13 +723,16 @@ int evolve_common(cc_ctx *c, cc_state *s, int64_t n, const int64_t *off, int32_t
             if (*c->h_err) rc = err_code(c, *c->h_err);
         }
         if (rc != CC_OK) {
+            hipStreamSynchronize(c->side);
             hipStreamSynchronize(c->st);
+            recycle_sync_events(c);
             for (int a = 0; a < 6; ++a)
                 hipMemcpyAsync(c->w[a], c->snap[a], bytes, hipMemcpyDeviceToDevice, c->st);
             break;
         }
         done = step + 1;
         if (c->timing) flush_timing(c);
+        recycle_sync_events(c);
     }
     // copy the working state back (slots are in entry order = particle order)
     for (int a = 0; a < 6; ++a) HIPCHK(hipMemcpyAsync(user[a], c->w[a], bytes, hipMemcpyDeviceToDevice, c->st));
@@ -699,7 +776,7 @@ int cc_create(cc_ctx **out, int32_t hip_device, const cc_params *p)
     }
     c->params = *p;
     c->device = hip_device;
-    c->levels.resize(64);  // fixed size: references to levels stay valid during the recursion
+    c->levels.resize(kLevels);  // fixed size: references to levels stay valid during the recursion
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || hip_device < 0 || hip_device >= ndev) {
         delete c;
@@ -712,7 +789,12 @@ int cc_create(cc_ctx **out, int32_t hip_device, const cc_params *p)
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
         c->cus = cus;
-    if (dalloc(c, &c->errf, 1) != CC_OK || halloc(c, &c->h_err, 1) != CC_OK || dalloc(c, &c->qhead, 1) != CC_OK ||
+    // default priority, no implicit synchronisation with the null stream
+    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return CC_ERR_DEVICE;
+    }
+    if (dalloc(c, &c->errf, 1) != CC_OK || halloc(c, &c->h_err, 1) != CC_OK || dalloc(c, &c->qhead, kLevels) != CC_OK ||
         dalloc(c, &c->diag_out, 16) != CC_OK || halloc(c, &c->h_diag, 16) != CC_OK ||
         dalloc(c, &c->fam_work, 2 * F_N) != CC_OK) {
         cc_destroy(c);
@@ -751,6 +833,9 @@ void cc_destroy(cc_ctx *c)
         hipEventDestroy(r.b);
     }
     for (auto e : c->ev_pool) hipEventDestroy(e);
+    for (auto e : c->sync_pool) hipEventDestroy(e);
+    for (auto e : c->sync_used) hipEventDestroy(e);
+    if (c->side) hipStreamDestroy(c->side);
     delete c;
 }
 
@@ -797,19 +882,21 @@ int cc_split_labels(cc_ctx *c, const cc_state *s, int64_t n, double h, int32_t *
     RC(ensure_level(c, 0, 1));
     Level &lv = c->levels[0];
     const int T = (int)((n + TPB - 1) / TPB);
+    const int64_t T64 = (n + SWEEP_TILE - 1) / SWEEP_TILE;
+    if (T64 * (T64 + 1) / 2 > INT32_MAX) return fail(c, CC_ERR_ARG, "n too large");
+    const int NT = (int)(T64 * (T64 + 1) / 2);
     lv.h_seg[0] = Seg{0, (int32_t)n, 0, 0};
     int32_t *o = lv.h_offs;
-    if ((int64_t)T * (T + 1) / 2 > INT32_MAX) return fail(c, CC_ERR_ARG, "n too large");
-    o[0] = 0; o[1] = T; o[2] = 0; o[3] = T * (T + 1) / 2; o[4] = 0; o[5] = (int32_t)n;
+    o[0] = 0; o[1] = T; o[2] = 0; o[3] = NT; o[4] = 0; o[5] = (int32_t)n;
     HIPCHK(hipMemcpyAsync(lv.seg, lv.h_seg, sizeof(Seg), hipMemcpyHostToDevice, c->st));
     HIPCHK(hipMemcpyAsync(lv.offs, lv.h_offs, 6 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
-    GridLevelArgs a{lv.seg, lv.offs, lv.offs + 2, lv.offs + 4, nullptr, nullptr, 1, T, T * (T + 1) / 2, (int)n, 0};
+    GridLevelArgs a{lv.seg, lv.offs, lv.offs + 2, lv.offs + 4, nullptr, nullptr, 1, T, NT, (int)n, 0};
     HIPCHK(hipMemsetAsync(c->stats, 0, ST_N * sizeof(uint64_t), c->st));
     HIPCHK(launch_fill_i32(lv.notstar, 1, 0, c->st));
     const DevParams p = dev_params(c);
     SoA S = user_soa(s);
-    HIPCHK(launch_star(S, a, lv.notstar, c->parent, c->cnt, p, h, c->stats, nullptr, c->st));
-    HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, c->stats, nullptr, c->st));
+    HIPCHK(launch_star(S, a, lv.notstar, c->parent, c->cnt, p, h, mixed(c), c->stats, nullptr, c->st));
+    HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, mixed(c), c->stats, nullptr, c->st));
     HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, c->cnt, c->stats, c->st));
     if (n_nontrivial_out) {
         // roots carry their component size in cnt (zeroed for every slot by the star kernel)

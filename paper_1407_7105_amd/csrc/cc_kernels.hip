@@ -116,29 +116,40 @@ __device__ __forceinline__ int32_t lload(const int32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+__device__ __forceinline__ void lstore(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Find with path halving: every pointer written is an ancestor of the node,
+// which keeps the structure valid under concurrent hooking.
 __device__ __forceinline__ int32_t lfind(int32_t *par, int32_t a)
 {
     for (int it = 0; it < FIND_BUDGET; ++it) {
         const int32_t q = lload(&par[a]);
         if (q == a) return a;
+        const int32_t g = lload(&par[q]);
+        if (g != q) lstore(&par[a], g);
         a = q;
     }
     return a;
 }
 
-__device__ __forceinline__ void lunite(int32_t *par, int32_t a, int32_t b)
+// Joins the sets of a and b; returns the root of the joined set (as seen now).
+__device__ __forceinline__ int32_t lunite(int32_t *par, int32_t a, int32_t b)
 {
     for (int it = 0; it < FIND_BUDGET; ++it) {
         a = lfind(par, a);
         b = lfind(par, b);
-        if (a == b) return;
+        if (a == b) return a;
         if (a > b) {
             const int32_t t = a;
             a = b;
             b = t;
         }
-        if (atomicCAS(&par[b], b, a) == b) return;
+        if (atomicCAS(&par[b], b, a) == b) return a;
     }
+    return a;
 }
 
 // ---------------------------------------------------------------------------
@@ -198,6 +209,7 @@ __global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v)
 // Star test (Sec. 2.3, fully connected case): with X the segment's first slot,
 // the segment is one component if tau(X,U) < h for every other U.  notstar[s]
 // is set when some U fails.  Also initialises the union-find arrays.
+template <bool MIXED>
 __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg,
                                                const int32_t *__restrict__ chunk_off, int nseg,
                                                int32_t *__restrict__ notstar, int32_t *__restrict__ parent,
@@ -216,8 +228,9 @@ __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg
         cnt[u] = 0;
         if (local > 0) {
             ev = 1;
-            if (!edge_pair(S.x[X] - S.x[u], S.y[X] - S.y[u], S.z[X] - S.z[u], S.vx[X] - S.vx[u],
-                           S.vy[X] - S.vy[u], S.vz[X] - S.vz[u], S.m[X] + S.m[u], p, h))
+            if (!edge_decide<MIXED>(S.x[X] - S.x[u], S.y[X] - S.y[u], S.z[X] - S.z[u], S.vx[X] - S.vx[u],
+                                    S.vy[X] - S.vy[u], S.vz[X] - S.vz[u], S.m[X] + S.m[u], p,
+                                    screen_params(p, h), h))
                 notstar[s] = 1;
         }
     }
@@ -229,84 +242,98 @@ __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg
 }
 
 // All-pairs sweep of a segment that failed the star test: for each pair
-// i<j with tau(i,j) < h, merge their sets.  One block per (i-tile, j-tile)
-// with i-tile <= j-tile.  Edges are first joined in a union-find local to the
-// block, in LDS, over the tile's 512 particles (256 when i-tile = j-tile);
-// each particle's global root is read once at tile start and an edge between
-// particles that already share it is skipped.  Afterwards every particle whose
-// local set root has a different global root is merged globally -- at most
-// one global union per particle per tile instead of one per edge.
+// i<j with tau(i,j) < h, merge their sets.  Work is cut into 64x64 tiles
+// (i tile <= j tile), one per wavefront, four per block.  A wavefront stages
+// its j tile in LDS, joins edges in a union-find local to the tile over its
+// 128 particles (64 when i tile = j tile), skipping an edge whose particles
+// already share the global root read at tile start, and finally merges each
+// particle whose local root has a different global root into the global
+// structure: at most one global union per particle per tile.
+constexpr int ST = 64;  // sweep tile edge (one wavefront)
+
+template <bool MIXED>
 __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ seg,
                                                 const int32_t *__restrict__ tile_off, int nseg,
                                                 const int32_t *__restrict__ notstar,
                                                 int32_t *__restrict__ parent, DevParams p, double h,
                                                 uint64_t *stats, uint64_t *fam)
 {
-    __shared__ double jx[TPB], jy[TPB], jz[TPB], jvx[TPB], jvy[TPB], jvz[TPB], jm[TPB];
-    __shared__ int32_t lpar[2 * TPB];
-    __shared__ int32_t groot[2 * TPB];
-    __shared__ uint64_t sh[4];
-    const int s = find_seg(tile_off, nseg, blockIdx.x);
-    if (!notstar[s]) return;
-    const Seg g = seg[s];
-    const int T = (g.n + TPB - 1) / TPB;
-    int t = blockIdx.x - tile_off[s];
-    int ti = 0;
-    while (t >= T - ti) {
-        t -= T - ti;
-        ti++;
+    constexpr int NW = TPB / ST;
+    __shared__ double jx[NW][ST], jy[NW][ST], jz[NW][ST], jvx[NW][ST], jvy[NW][ST], jvz[NW][ST], jm[NW][ST];
+    __shared__ int32_t lpar[NW][2 * ST];
+    __shared__ int32_t groot[NW][2 * ST];
+    const int w = threadIdx.x / ST, lane = threadIdx.x % ST;
+    const int tile = blockIdx.x * NW + w;
+    const int total = tile_off[nseg];
+    int s = 0, ti = 0, tj = 0, T = 0;
+    bool active = tile < total;
+    if (active) {
+        s = find_seg(tile_off, nseg, tile);
+        active = notstar[s] != 0;
     }
-    const int tj = ti + t;
+    Seg g{0, 0, 0, 0};
+    if (active) {
+        g = seg[s];
+        T = (g.n + ST - 1) / ST;
+        int t = tile - tile_off[s];
+        while (t >= T - ti) {
+            t -= T - ti;
+            ti++;
+        }
+        tj = ti + t;
+    }
     const bool diag = (ti == tj);
-    const int jbase = g.start + tj * TPB;
-    const int jn = min(TPB, g.n - tj * TPB);
-    const int il = ti * TPB + threadIdx.x;
-    const bool ivalid = il < g.n;
+    const int jn = active ? min(ST, g.n - tj * ST) : 0;
+    const int il = ti * ST + lane;
+    const bool ivalid = active && il < g.n;
     const int i = g.start + (ivalid ? il : 0);
-    lpar[threadIdx.x] = threadIdx.x;
-    lpar[TPB + threadIdx.x] = TPB + threadIdx.x;
-    groot[threadIdx.x] = ivalid ? gfind(parent, i) : -1;
-    groot[TPB + threadIdx.x] = -1;
-    if (threadIdx.x < jn) {
-        const int j = jbase + threadIdx.x;
-        jx[threadIdx.x] = S.x[j];
-        jy[threadIdx.x] = S.y[j];
-        jz[threadIdx.x] = S.z[j];
-        jvx[threadIdx.x] = S.vx[j];
-        jvy[threadIdx.x] = S.vy[j];
-        jvz[threadIdx.x] = S.vz[j];
-        jm[threadIdx.x] = S.m[j];
-        if (!diag) groot[TPB + threadIdx.x] = gfind(parent, j);
+    int32_t *lp = lpar[w];
+    int32_t *gr = groot[w];
+    lp[lane] = lane;
+    lp[ST + lane] = ST + lane;
+    gr[lane] = ivalid ? gfind(parent, i) : -1;
+    gr[ST + lane] = -1;
+    if (lane < jn) {
+        const int j = g.start + tj * ST + lane;
+        jx[w][lane] = S.x[j];
+        jy[w][lane] = S.y[j];
+        jz[w][lane] = S.z[j];
+        jvx[w][lane] = S.vx[j];
+        jvy[w][lane] = S.vy[j];
+        jvz[w][lane] = S.vz[j];
+        jm[w][lane] = S.m[j];
+        if (!diag) gr[ST + lane] = gfind(parent, j);
     }
     __syncthreads();
     uint64_t ev = 0;
     if (ivalid) {
         const double xi = S.x[i], yi = S.y[i], zi = S.z[i];
         const double vxi = S.vx[i], vyi = S.vy[i], vzi = S.vz[i], mi = S.m[i];
-        const int vi = threadIdx.x;
-        const int32_t gi = groot[vi];
-        const int j0 = diag ? threadIdx.x + 1 : 0;
-        const int joff = diag ? 0 : TPB;
+        const int32_t gi = gr[lane];
+        int32_t lr = lane;  // an ancestor of this particle in the local structure
+        const int j0 = diag ? lane + 1 : 0;
+        const int joff = diag ? 0 : ST;
+        const ScreenParams q = screen_params(p, h);
         ev = (jn > j0) ? (uint64_t)(jn - j0) : 0;
         for (int jj = j0; jj < jn; ++jj) {
-            if (edge_pair(xi - jx[jj], yi - jy[jj], zi - jz[jj], vxi - jvx[jj], vyi - jvy[jj], vzi - jvz[jj],
-                          mi + jm[jj], p, h)) {
+            if (edge_decide<MIXED>(xi - jx[w][jj], yi - jy[w][jj], zi - jz[w][jj], vxi - jvx[w][jj],
+                                   vyi - jvy[w][jj], vzi - jvz[w][jj], mi + jm[w][jj], p, q, h)) {
                 const int vj = joff + jj;
-                if (groot[vj] != gi) lunite(lpar, vi, vj);
+                if (gr[vj] != gi) lr = lunite(lp, lr, vj);
             }
         }
     }
     __syncthreads();
-    // merge the block's local sets into the global structure
-    for (int v = threadIdx.x; v < 2 * TPB; v += TPB) {
-        if (groot[v] < 0) continue;
-        const int r = lfind(lpar, v);
-        if (r != v && groot[r] != groot[v]) gunite(parent, groot[v], groot[r]);
+    // merge the tile's local sets into the global structure
+    for (int v = lane; v < 2 * ST; v += ST) {
+        if (gr[v] < 0) continue;
+        const int r = lfind(lp, v);
+        if (r != v && gr[r] != gr[v]) gunite(parent, gr[v], gr[r]);
     }
-    const uint64_t tot = block_sum_u64(ev, sh);
-    if (threadIdx.x == 0) {
-        stat_add(stats, g.cluster, ST_TAU, tot);
-        fam_add(fam, 0, tot);
+    ev = wave_sum_u64(ev);
+    if (lane == 0 && active) {
+        stat_add(stats, g.cluster, ST_TAU, ev);
+        fam_add(fam, 0, ev);
     }
 }
 
@@ -530,6 +557,7 @@ __global__ __launch_bounds__(TPB) void k_kick_seg(SoA W, const Seg *__restrict__
 // skipped whole (all its pairs are inside one component).  Each block writes
 // its partial accelerations; k_kick_combine adds the groups of every i in
 // group order, so the result is deterministic.
+template <bool MIXED>
 __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict__ seg,
                                                      const int32_t *__restrict__ kick_off,
                                                      const int32_t *__restrict__ kgrp, int nseg,
@@ -569,15 +597,30 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
             jx[threadIdx.x] = W.x[j];
             jy[threadIdx.x] = W.y[j];
             jz[threadIdx.x] = W.z[j];
-            jm[threadIdx.x] = W.m[j];
+            jm[threadIdx.x] = MIXED ? (double)(float)(G * W.m[j]) : W.m[j];
             jl[threadIdx.x] = labp[j];
         }
         __syncthreads();
         if (valid) {
-            for (int jj = 0; jj < jn; ++jj) {
-                if (jl[jj] == li) continue;
-                ok &= accel_term(xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, G, ax, ay, az);
-                pairs += (jb + jj > il);
+            if (MIXED) {
+                // FP32 forces on FP64 differences, Kahan-compensated within the
+                // tile, FP64 across tiles
+                Kahan3 k{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                const float e2 = (float)eps2;
+                for (int jj = 0; jj < jn; ++jj) {
+                    if (jl[jj] == li) continue;
+                    ok &= accel_term32(xi, yi, zi, jx[jj], jy[jj], jz[jj], (float)jm[jj], e2, k);
+                    pairs += (jb + jj > il);
+                }
+                ax += (double)k.sx - (double)k.cx;
+                ay += (double)k.sy - (double)k.cy;
+                az += (double)k.sz - (double)k.cz;
+            } else {
+                for (int jj = 0; jj < jn; ++jj) {
+                    if (jl[jj] == li) continue;
+                    ok &= accel_term(xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, G, ax, ay, az);
+                    pairs += (jb + jj > il);
+                }
             }
         }
     }
@@ -675,6 +718,7 @@ __global__ void k_apply_kick(SoA W, int n, const double *__restrict__ ax, const 
 // ---------------------------------------------------------------------------
 // Two-particle components, one per lane.
 // ---------------------------------------------------------------------------
+template <bool MIXED>
 __global__ __launch_bounds__(TPB) void k_pairs(SoA W, const Seg *__restrict__ items, const int32_t *__restrict__ count,
                                                 int cap, double H, DevParams p, int32_t *err, uint64_t *stats,
                                                 uint64_t *fam)
@@ -690,7 +734,7 @@ __global__ __launch_bounds__(TPB) void k_pairs(SoA W, const Seg *__restrict__ it
         Body a{W.x[ia], W.y[ia], W.z[ia], W.vx[ia], W.vy[ia], W.vz[ia], W.m[ia]};
         Body b{W.x[ib], W.y[ib], W.z[ib], W.vx[ib], W.vy[ib], W.vz[ib], W.m[ib]};
         PairCounters c{0, 0, 0, 0, 0, -1};
-        const int e = evolve_pair(a, b, H, g.depth, p, c);
+        const int e = evolve_pair<MIXED>(a, b, H, g.depth, p, c);
         if (e) atomicOr(err, e);
         W.x[ia] = a.x; W.y[ia] = a.y; W.z[ia] = a.z; W.vx[ia] = a.vx; W.vy[ia] = a.vy; W.vz[ia] = a.vz;
         W.x[ib] = b.x; W.y[ib] = b.y; W.z[ib] = b.z; W.vx[ib] = b.vx; W.vy[ib] = b.vy; W.vz[ib] = b.vz;
@@ -745,8 +789,12 @@ struct SmallLDS {
     int32_t maxd;
 };
 
-template <int CAP, bool EXACT>
+// MODE: 0 = FP64, partners in slot order; 1 = FP64, partners in ascending
+// particle index (bit-identical to a sequential sweep); 2 = mixed precision.
+template <int CAP, int MODE>
 struct SmallKernel {
+    static constexpr bool EXACT = (MODE == 1);
+    static constexpr bool MIXED = (MODE == 2);
     static constexpr int E = CAP / TPB;  // positions per thread
     static constexpr int W = CAP / 32;   // mask words
 
@@ -830,7 +878,7 @@ struct SmallKernel {
             }
             Body a{L.x[ia], L.y[ia], L.z[ia], L.vx[ia], L.vy[ia], L.vz[ia], L.m[ia]};
             Body b{L.x[ib], L.y[ib], L.z[ib], L.vx[ib], L.vy[ib], L.vz[ib], L.m[ib]};
-            const int e = evolve_pair(a, b, h, depth, p, c);
+            const int e = evolve_pair<MIXED>(a, b, h, depth, p, c);
             if (e) atomicOr(&L.err, e);
             L.x[ia] = a.x; L.y[ia] = a.y; L.z[ia] = a.z; L.vx[ia] = a.vx; L.vy[ia] = a.vy; L.vz[ia] = a.vz;
             L.x[ib] = b.x; L.y[ib] = b.y; L.z[ib] = b.z; L.vx[ib] = b.vx; L.vy[ib] = b.vy; L.vz[ib] = b.vz;
@@ -890,6 +938,7 @@ struct SmallKernel {
         for (int q = threadIdx.x; q < CAP; q += TPB) L.cnt[q] = 0;
         __syncthreads();
         unsigned long long tau = 0;
+        const ScreenParams sq = screen_params(p, h);
         // star test from each set's first position X
         for (int q = threadIdx.x; q < n; q += TPB) {
             if (!is_main(L, q)) continue;
@@ -897,8 +946,8 @@ struct SmallKernel {
             const int X = L.segS[q];
             if (q == X) continue;
             tau++;
-            if (!edge_pair(L.x[X] - L.x[q], L.y[X] - L.y[q], L.z[X] - L.z[q], L.vx[X] - L.vx[q],
-                           L.vy[X] - L.vy[q], L.vz[X] - L.vz[q], L.m[X] + L.m[q], p, h))
+            if (!edge_decide<MIXED>(L.x[X] - L.x[q], L.y[X] - L.y[q], L.z[X] - L.z[q], L.vx[X] - L.vx[q],
+                                    L.vy[X] - L.vy[q], L.vz[X] - L.vz[q], L.m[X] + L.m[q], p, sq, h))
                 atomicOr(&L.flag[X >> 5], 1u << (X & 31));
         }
         __syncthreads();
@@ -911,8 +960,8 @@ struct SmallKernel {
             const double xa = L.x[a], ya = L.y[a], za = L.z[a], vxa = L.vx[a], vya = L.vy[a], vza = L.vz[a],
                          ma = L.m[a];
             for (int b = a + 1; b < e; ++b) {
-                if (edge_pair(xa - L.x[b], ya - L.y[b], za - L.z[b], vxa - L.vx[b], vya - L.vy[b],
-                              vza - L.vz[b], ma + L.m[b], p, h))
+                if (edge_decide<MIXED>(xa - L.x[b], ya - L.y[b], za - L.z[b], vxa - L.vx[b], vya - L.vy[b],
+                                       vza - L.vz[b], ma + L.m[b], p, sq, h))
                     lunite(L.par, a, b);
             }
             tau += (unsigned long long)(e - a - 1);
@@ -1043,11 +1092,24 @@ struct SmallKernel {
             const int ca = L.cid[a];
             const int oa = L.orig[a];
             double ax = 0.0, ay = 0.0, az = 0.0;
-            for (int t = s; t < e; ++t) {
-                const int q = EXACT ? L.aux[t] : t;
-                if (L.cid[q] == ca) continue;
-                ok &= accel_term(xa, ya, za, L.x[q], L.y[q], L.z[q], L.m[q], p.eps2, p.G, ax, ay, az);
-                kicks += (L.orig[q] > oa);
+            if (MIXED) {
+                Kahan3 kh{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                const float e2 = (float)p.eps2;
+                for (int q = s; q < e; ++q) {
+                    if (L.cid[q] == ca) continue;
+                    ok &= accel_term32(xa, ya, za, L.x[q], L.y[q], L.z[q], (float)(p.G * L.m[q]), e2, kh);
+                    kicks += (L.orig[q] > oa);
+                }
+                ax = (double)kh.sx - (double)kh.cx;
+                ay = (double)kh.sy - (double)kh.cy;
+                az = (double)kh.sz - (double)kh.cz;
+            } else {
+                for (int t = s; t < e; ++t) {
+                    const int q = EXACT ? L.aux[t] : t;
+                    if (L.cid[q] == ca) continue;
+                    ok &= accel_term(xa, ya, za, L.x[q], L.y[q], L.z[q], L.m[q], p.eps2, p.G, ax, ay, az);
+                    kicks += (L.orig[q] > oa);
+                }
             }
             // velocities are not read by the kick, so each thread updates its own
             L.vx[a] += h * ax;
@@ -1168,7 +1230,7 @@ struct SmallItems {
     int32_t cap;
 };
 
-template <int CAP, bool EXACT>
+template <int CAP, int MODE>
 __global__ __launch_bounds__(TPB) void k_small(SoA W, SmallItems items, int32_t *qhead, double H, DevParams p,
                                                 int32_t *err, uint64_t *stats, uint64_t *fam)
 {
@@ -1206,7 +1268,7 @@ __global__ __launch_bounds__(TPB) void k_small(SoA W, SmallItems items, int32_t 
             }
             continue;
         }
-        SmallKernel<CAP, EXACT>::run_item(W, L, g, H, p, err, stats, fam);
+        SmallKernel<CAP, MODE>::run_item(W, L, g, H, p, err, stats, fam);
     }
 }
 
@@ -1346,19 +1408,28 @@ hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t st)
 }
 
 hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, int32_t *cnt, DevParams p,
-                       double h, uint64_t *stats, uint64_t *fam, hipStream_t st)
+                       double h, bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_star, dim3(a.nchunks), dim3(TPB), 0, st, S, a.seg, a.chunk_off, a.nseg, notstar, parent, cnt,
-                       p, h, stats, fam);
+    if (mixed)
+        hipLaunchKernelGGL(k_star<true>, dim3(a.nchunks), dim3(TPB), 0, st, S, a.seg, a.chunk_off, a.nseg, notstar,
+                           parent, cnt, p, h, stats, fam);
+    else
+        hipLaunchKernelGGL(k_star<false>, dim3(a.nchunks), dim3(TPB), 0, st, S, a.seg, a.chunk_off, a.nseg, notstar,
+                           parent, cnt, p, h, stats, fam);
     return hipGetLastError();
 }
 
 hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, DevParams p, double h,
-                        uint64_t *stats, uint64_t *fam, hipStream_t st)
+                        bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
     if (a.ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sweep, dim3(a.ntiles), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar, parent, p,
-                       h, stats, fam);
+    const int nb = (a.ntiles + TPB / ST - 1) / (TPB / ST);
+    if (mixed)
+        hipLaunchKernelGGL(k_sweep<true>, dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar, parent,
+                           p, h, stats, fam);
+    else
+        hipLaunchKernelGGL(k_sweep<false>, dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar, parent,
+                           p, h, stats, fam);
     return hipGetLastError();
 }
 
@@ -1453,10 +1524,14 @@ hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, 
 }
 
 hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const int32_t *labp, double h, double eps2, double G,
-                             double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
+                             bool mixed, double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_kick_tiles, dim3(a.nkblocks), dim3(TPB), 0, st, W, a.seg, a.kick_off, a.kgrp, a.nseg, labp,
-                       eps2, G, part, err, stats, fam);
+    if (mixed)
+        hipLaunchKernelGGL(k_kick_tiles<true>, dim3(a.nkblocks), dim3(TPB), 0, st, W, a.seg, a.kick_off, a.kgrp,
+                           a.nseg, labp, eps2, G, part, err, stats, fam);
+    else
+        hipLaunchKernelGGL(k_kick_tiles<false>, dim3(a.nkblocks), dim3(TPB), 0, st, W, a.seg, a.kick_off, a.kgrp,
+                           a.nseg, labp, eps2, G, part, err, stats, fam);
     hipLaunchKernelGGL(k_kick_combine, dim3(a.nchunks), dim3(TPB), 0, st, W, a.seg, a.chunk_off, a.kick_off, a.kgrp,
                        a.nseg, (const double *)part, h);
     return hipGetLastError();
@@ -1477,22 +1552,26 @@ hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, c
 }
 
 hipError_t launch_pairs(SoA W, const Seg *items, const int32_t *count, int cap, int nitems, double H, DevParams p,
-                        int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
+                        bool mixed, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pairs, dim3(nblocks(nitems, 4096)), dim3(TPB), 0, st, W, items, count, cap, H, p, err,
-                       stats, fam);
+    if (mixed)
+        hipLaunchKernelGGL(k_pairs<true>, dim3(nblocks(nitems, 4096)), dim3(TPB), 0, st, W, items, count, cap, H, p,
+                           err, stats, fam);
+    else
+        hipLaunchKernelGGL(k_pairs<false>, dim3(nblocks(nitems, 4096)), dim3(TPB), 0, st, W, items, count, cap, H, p,
+                           err, stats, fam);
     return hipGetLastError();
 }
 
-template <int CAP, bool EXACT>
+template <int CAP, int MODE>
 static hipError_t launch_small_cap(SoA W, const SmallArgs &s, double H, DevParams p, int32_t *err, uint64_t *stats,
                                    uint64_t *fam, int nblk, hipStream_t st)
 {
     static bool configured = false;
     const size_t lds = sizeof(SmallLDS<CAP>);
     if (!configured) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_small<CAP, EXACT>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_small<CAP, MODE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         configured = true;
@@ -1501,7 +1580,7 @@ static hipError_t launch_small_cap(SoA W, const SmallArgs &s, double H, DevParam
     for (int b = 0; b < 4; ++b) it.bin[b] = s.bin[b];
     it.count = s.count;
     it.cap = s.cap;
-    hipLaunchKernelGGL((k_small<CAP, EXACT>), dim3(nblk), dim3(TPB), lds, st, W, it, s.qhead, H, p, err, stats, fam);
+    hipLaunchKernelGGL((k_small<CAP, MODE>), dim3(nblk), dim3(TPB), lds, st, W, it, s.qhead, H, p, err, stats, fam);
     return hipGetLastError();
 }
 
@@ -1512,18 +1591,22 @@ size_t small_lds_bytes(int cap)
     return sizeof(SmallLDS<1024>);
 }
 
-hipError_t launch_small(SoA W, const SmallArgs &s, int cap, bool exact, double H, DevParams p, int32_t *err,
+hipError_t launch_small(SoA W, const SmallArgs &s, int cap, int mode, double H, DevParams p, int32_t *err,
                         uint64_t *stats, uint64_t *fam, int nblk, hipStream_t st)
 {
     if (nblk <= 0) return hipSuccess;
-    if (exact) {
-        if (cap <= 256) return launch_small_cap<256, true>(W, s, H, p, err, stats, fam, nblk, st);
-        if (cap <= 512) return launch_small_cap<512, true>(W, s, H, p, err, stats, fam, nblk, st);
-        return launch_small_cap<1024, true>(W, s, H, p, err, stats, fam, nblk, st);
+#define CC_SMALL_CAPS(M)                                                                  \
+    if (cap <= 256) return launch_small_cap<256, M>(W, s, H, p, err, stats, fam, nblk, st); \
+    if (cap <= 512) return launch_small_cap<512, M>(W, s, H, p, err, stats, fam, nblk, st); \
+    return launch_small_cap<1024, M>(W, s, H, p, err, stats, fam, nblk, st);
+    if (mode == 1) {
+        CC_SMALL_CAPS(1)
     }
-    if (cap <= 256) return launch_small_cap<256, false>(W, s, H, p, err, stats, fam, nblk, st);
-    if (cap <= 512) return launch_small_cap<512, false>(W, s, H, p, err, stats, fam, nblk, st);
-    return launch_small_cap<1024, false>(W, s, H, p, err, stats, fam, nblk, st);
+    if (mode == 2) {
+        CC_SMALL_CAPS(2)
+    }
+    CC_SMALL_CAPS(0)
+#undef CC_SMALL_CAPS
 }
 
 int diag_blocks(int n) { return nblocks(n, 1 << 30); }

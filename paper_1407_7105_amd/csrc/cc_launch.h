@@ -53,9 +53,9 @@ hipError_t launch_iota(int32_t *a, int64_t n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t st);
 
 hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, int32_t *cnt, DevParams p,
-                       double h, uint64_t *stats, uint64_t *fam, hipStream_t st);
+                       double h, bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st);
 hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, DevParams p, double h,
-                        uint64_t *stats, uint64_t *fam, hipStream_t st);
+                        bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st);
 hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,
                         uint64_t *stats, hipStream_t st);
 hipError_t launch_keys(const GridLevelArgs &a, const int32_t *label, uint32_t *keys, uint32_t *vals, hipStream_t st);
@@ -73,15 +73,16 @@ hipError_t launch_drift_seg(SoA W, const GridLevelArgs &a, const uint8_t *sing, 
 hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, double h, double eps2, double G,
                            int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
 hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const int32_t *labp, double h, double eps2, double G,
-                             double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
+                             bool mixed, double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
 hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, double *ax, double *ay,
                            double *az, int32_t *err, hipStream_t st);
 hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, const double *az, double h,
                              hipStream_t st);
 hipError_t launch_pairs(SoA W, const Seg *items, const int32_t *count, int cap, int nitems, double H, DevParams p,
-                        int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
+                        bool mixed, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
 size_t small_lds_bytes(int cap);
-hipError_t launch_small(SoA W, const SmallArgs &s, int cap, bool exact, double H, DevParams p, int32_t *err,
+// mode: 0 = FP64 slot order, 1 = FP64 ascending index order, 2 = mixed precision
+hipError_t launch_small(SoA W, const SmallArgs &s, int cap, int mode, double H, DevParams p, int32_t *err,
                         uint64_t *stats, uint64_t *fam, int nblk, hipStream_t st);
 int diag_blocks(int n);
 hipError_t launch_diag(SoA S, int n, double eps2, double G, double *part, double *out, hipStream_t st);

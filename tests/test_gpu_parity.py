@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_1407_7105_amd import CC_ORDER_EXACT, CC_ORDER_FAST, CCError, Context, State  # noqa: E402
+from paper_1407_7105_amd import CC_FP64, CC_MIXED, CC_ORDER_EXACT, CC_ORDER_FAST, CCError, Context, State  # noqa: E402
 
 
 def ctx_for(p: oracle.Params, **kw):
@@ -68,8 +68,8 @@ def test_pair_timesteps_wide_dynamic_range():
 
 # ------------------------------------------------------------------ split
 
-def check_split(s, h, p, ctx=None):
-    ctx = ctx or ctx_for(p)
+def check_split(s, h, p, ctx=None, precision=CC_FP64):
+    ctx = ctx or ctx_for(p, precision=precision)
     lab, nt = ctx.split_labels(State.from_numpy(s), h)
     want, want_nt, _ = oracle.split_labels(s, h, p)
     assert np.array_equal(lab.cpu().numpy(), want)
@@ -77,13 +77,14 @@ def check_split(s, h, p, ctx=None):
     return want_nt
 
 
+@pytest.mark.parametrize("precision", [CC_FP64, CC_MIXED])
 @pytest.mark.parametrize("n,seed", [(3, 1), (255, 2), (256, 3), (257, 4), (700, 5), (3000, 6)])
-def test_split_labels_bitwise(n, seed):
+def test_split_labels_bitwise(n, seed, precision):
     s = random_set(n, seed)
     p = oracle.Params(eta=0.01)
     tau = oracle.pair_timesteps(s, *synth.random_pairs(n, 4000, seed), p)
     for q in (0.001, 0.01, 0.1, 0.5, 0.99):
-        check_split(s, float(np.quantile(tau, q)), p)
+        check_split(s, float(np.quantile(tau, q)), p, precision=precision)
 
 
 def test_split_fully_connected_and_all_singletons():
@@ -93,20 +94,41 @@ def test_split_fully_connected_and_all_singletons():
     assert check_split(s, 1e-12, p) == 0
 
 
-def test_split_exact_threshold_ties():
+@pytest.mark.parametrize("precision", [CC_FP64, CC_MIXED])
+def test_split_exact_threshold_ties(precision):
     s = random_set(300, 13)
     p = oracle.Params(eta=0.01)
     pi, pj = synth.random_pairs(300, 50, 13)
     taus = oracle.pair_timesteps(s, pi, pj, p)
     for t in taus[:10]:
-        check_split(s, float(t), p)
-        check_split(s, float(np.nextafter(t, np.inf)), p)
+        check_split(s, float(t), p, precision=precision)
+        check_split(s, float(np.nextafter(t, np.inf)), p, precision=precision)
+        check_split(s, float(np.nextafter(t, 0.0)), p, precision=precision)
 
 
+def test_mixed_split_wide_dynamic_range():
+    """The FP32 screen must hand every pair it cannot decide (ranges, zero
+    relative velocity, near-threshold) to the FP64 formula."""
+    rng = np.random.default_rng(19)
+    n = 1500
+    pos = rng.normal(size=(n, 3)) * 10.0 ** rng.uniform(-9, 3, (n, 1))
+    vel = rng.normal(size=(n, 3)) * 10.0 ** rng.uniform(-9, 4, (n, 1))
+    vel[:40] = 0.0
+    pos[40:50] = pos[50:60]  # coincident pairs
+    s = Particles.from_arrays(pos, vel, 10.0 ** rng.uniform(-14, 0, n))
+    for eta, eps2 in ((0.01, 0.0), (0.03, 1e-12), (1.0, 0.0)):
+        p = oracle.Params(eta=eta, eps2=eps2)
+        tau = oracle.pair_timesteps(s, *synth.random_pairs(n, 4000, 7), p)
+        tau = tau[np.isfinite(tau) & (tau > 0)]
+        for q in (0.01, 0.3, 0.7, 0.99):
+            check_split(s, float(np.quantile(tau, q)), p, precision=CC_MIXED)
+
+
+@pytest.mark.parametrize("precision", [CC_FP64, CC_MIXED])
 @pytest.mark.parametrize("cfg,h", [(1, 1 / 64), (1, 1 / 1024), (2, 1 / 64), (2, 1 / 4096)])
-def test_split_workloads(cfg, h):
+def test_split_workloads(cfg, h, precision):
     s = synth.workload(cfg)
-    check_split(s, h, oracle.Params(eta=0.01))
+    check_split(s, h, oracle.Params(eta=0.01), precision=precision)
 
 
 # ------------------------------------------------------------------ kick / drift
@@ -349,3 +371,47 @@ def test_fast_order_one_step_lockstep(cfg, n, small_max):
     rel_close(g.to_numpy(), ref, 1e-10, f"cfg{cfg}")
     for k in STAT_KEYS:
         assert st[k] == ost[k], (k, st[k], ost[k])
+
+
+# ------------------------------------------------------------------ mixed precision
+
+def test_mixed_kick_all_slow_level():
+    """FP32 pair forces with compensated sums: velocity changes of an all-slow
+    leapfrog step agree with FP64 to 1e-6 of the kick (rms well below)."""
+    n = 3000
+    rng = np.random.default_rng(n)
+    # at rest, so the velocity after the step is exactly the kick h * a
+    s = Particles.from_arrays(rng.uniform(-1, 1, (n, 3)) * 10, np.zeros((n, 3)), rng.uniform(1, 2, n) * 1e-12)
+    p = oracle.Params(eta=0.01)
+    lab, nt, _ = oracle.split_labels(s, 1 / 64, p)
+    assert nt == 0
+    ref = s.copy()
+    oracle.evolve(ref, 1 / 64, 1 / 64, p)
+    g = State.from_numpy(s)
+    ctx_for(p, precision=CC_MIXED, small_max=64).evolve(g, 1 / 64, 1 / 64)
+    got = g.to_numpy()
+    dv_ref = np.stack([getattr(ref, f) - getattr(s, f) for f in ("vx", "vy", "vz")], 1)
+    dv = np.stack([got[f] - getattr(s, f) for f in ("vx", "vy", "vz")], 1)
+    err = np.linalg.norm(dv - dv_ref, axis=1) / np.linalg.norm(dv_ref, axis=1)
+    assert err.max() < 1e-6 and np.sqrt(np.mean(err ** 2)) < 1e-7
+
+
+@pytest.mark.parametrize("cfg,n", [(1, None), (2, 2000)])
+def test_mixed_step_conservation_and_accuracy(cfg, n):
+    """A mixed-precision step: close to the FP64 oracle, momentum and energy
+    conserved to FP32-compensated accuracy."""
+    s = synth.workload(cfg, n=n) if n else synth.workload(cfg)
+    p = oracle.Params(eta=0.01)
+    ref = s.copy()
+    oracle.evolve(ref, 1 / 64, 1 / 64, p)
+    g = State.from_numpy(s)
+    ctx = ctx_for(p, precision=CC_MIXED)
+    ctx.evolve(g, 1 / 64, 1 / 64)
+    got = g.to_numpy()
+    rel_close(got, ref, 1e-5, "mixed")
+    d0 = oracle.diagnostics(s, p)
+    gp = Particles(**got)
+    d1 = oracle.diagnostics(gp, p)
+    pscale = np.sum(s.m * np.linalg.norm(s.vel(), axis=1))
+    assert np.all(np.abs(d1["P"] - d0["P"]) < 1e-6 * pscale)
+    assert abs(d1["energy"] / d0["energy"] - 1) < 1e-5
