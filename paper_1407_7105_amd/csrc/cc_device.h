@@ -8,6 +8,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#define CC_SCREEN64_FN __device__ __forceinline__
+#define CC_SCREEN64_RSQ(x) __builtin_amdgcn_rsq(x)
+#include "cc_screen64.h"
+
 namespace ccg {
 
 struct DevParams {
@@ -208,16 +212,45 @@ __device__ __forceinline__ ScreenParams screen_params(const DevParams &p, double
     return q;
 }
 
-// Edge decision of eq. 20 with the FP32 screen in front of the FP64 formula.
+// Edge decision of eq. 20: the certified FP64 screen (and, in mixed
+// precision, the FP32 screen before it) in front of the literal formula.
 template <bool MIXED>
 __device__ __forceinline__ bool edge_decide(double dx, double dy, double dz, double dvx, double dvy, double dvz,
-                                            double msum, const DevParams &p, const ScreenParams &q, double h)
+                                            double msum, const DevParams &p, const ScreenParams &q,
+                                            const ccs::Screen64 &s64, double h)
 {
     if (MIXED) {
         const int sc = edge_screen32(dx, dy, dz, dvx, dvy, dvz, msum, q);
         if (sc != SCREEN_UNSURE) return sc == SCREEN_EDGE;
     }
+    const double r2 = ((dx * dx + dy * dy) + dz * dz) + p.eps2;
+    const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
+    const double rv = (dx * dvx + dy * dvy) + dz * dvz;
+    const double mu = p.G * msum;
+    const int sc = ccs::screen64(r2, v2, rv, mu, s64);
+    if (sc != ccs::SCREEN64_UNSURE) return sc == ccs::SCREEN64_EDGE;
     return edge_pair(dx, dy, dz, dvx, dvy, dvz, msum, p, h);
+}
+
+// Screen verdict for one pair (ccs::SCREEN64_NO / _EDGE / _UNSURE): the FP32
+// screen in mixed precision, the FP64 screen for what it leaves open.
+template <bool MIXED>
+__device__ __forceinline__ int edge_screen(double dx, double dy, double dz, double dvx, double dvy, double dvz,
+                                           double msum, const DevParams &p, const ScreenParams &q,
+                                           const ccs::Screen64 &s64)
+{
+    static_assert((int)SCREEN_NO == (int)ccs::SCREEN64_NO && (int)SCREEN_EDGE == (int)ccs::SCREEN64_EDGE &&
+                      (int)SCREEN_UNSURE == (int)ccs::SCREEN64_UNSURE,
+                  "screen verdict codes");
+    if (MIXED) {
+        const int sc = edge_screen32(dx, dy, dz, dvx, dvy, dvz, msum, q);
+        if (sc != SCREEN_UNSURE) return sc;
+    }
+    const double r2 = ((dx * dx + dy * dy) + dz * dz) + p.eps2;
+    const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
+    const double rv = (dx * dvx + dy * dvy) + dz * dvz;
+    const double mu = p.G * msum;
+    return ccs::screen64(r2, v2, rv, mu, s64);
 }
 
 // FP32 pair force on an FP64 coordinate difference (mixed kick): adds
@@ -266,6 +299,30 @@ __device__ __forceinline__ bool accel_term(double xi, double yi, double zi, doub
     return r2 != 0.0;
 }
 
+// The same pair term for the fast kick order, which is compared with the
+// sequential FP64 sum to a tolerance rather than bit for bit: 1/r from the
+// hardware reciprocal square root (about 2^-23 relative) and two Newton steps
+// (about 2^-46, then rounding level), no division; gmj = G m_j.
+__device__ __forceinline__ bool accel_term_rsq(double xi, double yi, double zi, double xj, double yj,
+                                               double zj, double gmj, double eps2, double &ax, double &ay,
+                                               double &az)
+{
+    const double dx = xj - xi;
+    const double dy = yj - yi;
+    const double dz = zj - zi;
+    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
+    double y = __builtin_amdgcn_rsq(r2);
+    double e = __builtin_fma(-(r2 * y), y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-(r2 * y), y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    const double f = gmj * (y * (y * y));
+    ax = __builtin_fma(f, dx, ax);
+    ay = __builtin_fma(f, dy, ay);
+    az = __builtin_fma(f, dz, az);
+    return r2 != 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // Two-particle evolve_cc, the recursion of Fig. 2 for a component {a, b}:
 // split at h is either one component (recurse twice at h/2) or two singletons
@@ -300,7 +357,8 @@ __device__ inline int evolve_pair(Body &a, Body &b, double H, int32_t depth0, co
         c.split++;
         c.tau++;
         const bool e = edge_decide<MIXED>(a.x - b.x, a.y - b.y, a.z - b.z, a.vx - b.vx, a.vy - b.vy,
-                                          a.vz - b.vz, msum, p, screen_params(p, h), h);
+                                          a.vz - b.vz, msum, p, screen_params(p, h),
+                                          ccs::screen64_params(p.eta, h), h);
         if (e && lvl < 63) {
             c.comp++;
             lvl++;

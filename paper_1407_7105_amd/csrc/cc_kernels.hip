@@ -13,6 +13,7 @@
 namespace ccg {
 
 constexpr int TPB = 256;  // threads per block everywhere (4 wave64)
+constexpr int WAVE = 64;  // wavefront width on gfx950
 
 // Largest s in [0, nseg) with off[s] <= b (off is a prefix-sum array).
 __device__ __forceinline__ int find_seg(const int32_t *off, int nseg, int b)
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg
             ev = 1;
             if (!edge_decide<MIXED>(S.x[X] - S.x[u], S.y[X] - S.y[u], S.z[X] - S.z[u], S.vx[X] - S.vx[u],
                                     S.vy[X] - S.vy[u], S.vz[X] - S.vz[u], S.m[X] + S.m[u], p,
-                                    screen_params(p, h), h))
+                                    screen_params(p, h), ccs::screen64_params(p.eta, h), h))
                 notstar[s] = 1;
         }
     }
@@ -306,21 +307,43 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
     }
     __syncthreads();
     uint64_t ev = 0;
-    if (ivalid) {
+    if (active) {
         const double xi = S.x[i], yi = S.y[i], zi = S.z[i];
         const double vxi = S.vx[i], vyi = S.vy[i], vzi = S.vz[i], mi = S.m[i];
+        const ScreenParams q = screen_params(p, h);
+        const ccs::Screen64 s64 = ccs::screen64_params(p.eta, h);
+        // Decide every pair of the tile first (one bit per partner: edge, or
+        // left to the literal formula), with a loop that is uniform across
+        // the wavefront; then resolve the undecided pairs and link the edges.
+        uint64_t emask = 0, umask = 0;
+        for (int jj = 0; jj < jn; ++jj) {
+            const int d = edge_screen<MIXED>(xi - jx[w][jj], yi - jy[w][jj], zi - jz[w][jj], vxi - jvx[w][jj],
+                                             vyi - jvy[w][jj], vzi - jvz[w][jj], mi + jm[w][jj], p, q, s64);
+            const uint64_t bit = 1ull << jj;
+            emask |= (d == ccs::SCREEN64_EDGE) ? bit : 0ull;
+            umask |= (d == ccs::SCREEN64_UNSURE) ? bit : 0ull;
+        }
+        // partners of this lane: j > i on the diagonal tile, all j otherwise
+        const uint64_t keep = !ivalid ? 0ull : !diag ? ~0ull : (lane >= ST - 1) ? 0ull : (~0ull << (lane + 1));
+        emask &= keep;
+        umask &= keep;
+        const int j0 = diag ? lane + 1 : 0;
+        ev = (ivalid && jn > j0) ? (uint64_t)(jn - j0) : 0;
+        while (umask) {
+            const int jj = __builtin_ctzll(umask);
+            umask &= umask - 1;
+            if (edge_pair(xi - jx[w][jj], yi - jy[w][jj], zi - jz[w][jj], vxi - jvx[w][jj], vyi - jvy[w][jj],
+                          vzi - jvz[w][jj], mi + jm[w][jj], p, h))
+                emask |= 1ull << jj;
+        }
         const int32_t gi = gr[lane];
         int32_t lr = lane;  // an ancestor of this particle in the local structure
-        const int j0 = diag ? lane + 1 : 0;
         const int joff = diag ? 0 : ST;
-        const ScreenParams q = screen_params(p, h);
-        ev = (jn > j0) ? (uint64_t)(jn - j0) : 0;
-        for (int jj = j0; jj < jn; ++jj) {
-            if (edge_decide<MIXED>(xi - jx[w][jj], yi - jy[w][jj], zi - jz[w][jj], vxi - jvx[w][jj],
-                                   vyi - jvy[w][jj], vzi - jvz[w][jj], mi + jm[w][jj], p, q, h)) {
-                const int vj = joff + jj;
-                if (gr[vj] != gi) lr = lunite(lp, lr, vj);
-            }
+        while (emask) {
+            const int jj = __builtin_ctzll(emask);
+            emask &= emask - 1;
+            const int vj = joff + jj;
+            if (gr[vj] != gi) lr = lunite(lp, lr, vj);
         }
     }
     __syncthreads();
@@ -347,11 +370,23 @@ __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, cons
     const Seg g = seg[s];
     const int local = (blockIdx.x - chunk_off[s]) * TPB + threadIdx.x;
     const bool ns = notstar[s] != 0;
-    if (local < g.n) {
+    const bool valid = local < g.n;
+    int32_t l = -1;
+    if (valid) {
         const int u = g.start + local;
-        const int32_t l = ns ? gfind(parent, u) : g.start;
+        l = ns ? gfind(parent, u) : g.start;
         label[u] = l;
-        atomicAdd(&cnt[l], 1);
+    }
+    // component sizes: one atomic per distinct label of the wavefront (a
+    // large component fills whole wavefronts with one label)
+    const int lane = threadIdx.x % WAVE;
+    uint64_t pending = __ballot(valid);
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int32_t ll = __shfl(l, leader, WAVE);
+        const uint64_t same = __ballot(valid && l == ll) & pending;
+        if (lane == leader) atomicAdd(&cnt[ll], (int32_t)__popcll(same));
+        pending &= ~same;
     }
     if (local == 0) {
         const uint64_t n = (uint64_t)g.n;
@@ -597,7 +632,7 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
             jx[threadIdx.x] = W.x[j];
             jy[threadIdx.x] = W.y[j];
             jz[threadIdx.x] = W.z[j];
-            jm[threadIdx.x] = MIXED ? (double)(float)(G * W.m[j]) : W.m[j];
+            jm[threadIdx.x] = MIXED ? (double)(float)(G * W.m[j]) : G * W.m[j];
             jl[threadIdx.x] = labp[j];
         }
         __syncthreads();
@@ -618,7 +653,7 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
             } else {
                 for (int jj = 0; jj < jn; ++jj) {
                     if (jl[jj] == li) continue;
-                    ok &= accel_term(xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, G, ax, ay, az);
+                    ok &= accel_term_rsq(xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, ax, ay, az);
                     pairs += (jb + jj > il);
                 }
             }
@@ -939,6 +974,7 @@ struct SmallKernel {
         __syncthreads();
         unsigned long long tau = 0;
         const ScreenParams sq = screen_params(p, h);
+        const ccs::Screen64 s64 = ccs::screen64_params(p.eta, h);
         // star test from each set's first position X
         for (int q = threadIdx.x; q < n; q += TPB) {
             if (!is_main(L, q)) continue;
@@ -947,7 +983,7 @@ struct SmallKernel {
             if (q == X) continue;
             tau++;
             if (!edge_decide<MIXED>(L.x[X] - L.x[q], L.y[X] - L.y[q], L.z[X] - L.z[q], L.vx[X] - L.vx[q],
-                                    L.vy[X] - L.vy[q], L.vz[X] - L.vz[q], L.m[X] + L.m[q], p, sq, h))
+                                    L.vy[X] - L.vy[q], L.vz[X] - L.vz[q], L.m[X] + L.m[q], p, sq, s64, h))
                 atomicOr(&L.flag[X >> 5], 1u << (X & 31));
         }
         __syncthreads();
@@ -961,7 +997,7 @@ struct SmallKernel {
                          ma = L.m[a];
             for (int b = a + 1; b < e; ++b) {
                 if (edge_decide<MIXED>(xa - L.x[b], ya - L.y[b], za - L.z[b], vxa - L.vx[b], vya - L.vy[b],
-                                       vza - L.vz[b], ma + L.m[b], p, sq, h))
+                                       vza - L.vz[b], ma + L.m[b], p, sq, s64, h))
                     lunite(L.par, a, b);
             }
             tau += (unsigned long long)(e - a - 1);
@@ -1107,7 +1143,10 @@ struct SmallKernel {
                 for (int t = s; t < e; ++t) {
                     const int q = EXACT ? L.aux[t] : t;
                     if (L.cid[q] == ca) continue;
-                    ok &= accel_term(xa, ya, za, L.x[q], L.y[q], L.z[q], L.m[q], p.eps2, p.G, ax, ay, az);
+                    if (EXACT)
+                        ok &= accel_term(xa, ya, za, L.x[q], L.y[q], L.z[q], L.m[q], p.eps2, p.G, ax, ay, az);
+                    else
+                        ok &= accel_term_rsq(xa, ya, za, L.x[q], L.y[q], L.z[q], p.G * L.m[q], p.eps2, ax, ay, az);
                     kicks += (L.orig[q] > oa);
                 }
             }

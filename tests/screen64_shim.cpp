@@ -1,0 +1,28 @@
+// Host build of the device FP64 edge screen, for checking on the CPU that every
+// decision it takes equals the literal FP64 edge test of the oracle.
+#define CC_SCREEN64_FN static inline
+// a deliberately coarse reciprocal square root (about 2^-23, like a hardware
+// seed): the screen must certify its refined roots by itself
+#define CC_SCREEN64_RSQ(x) ((double)(1.0f / __builtin_sqrtf((float)(x))))
+#include "../paper_1407_7105_amd/csrc/cc_screen64.h"
+
+#include <stdint.h>
+
+extern "C" void screen64_pairs(const double *x, const double *y, const double *z, const double *vx,
+                               const double *vy, const double *vz, const double *m, const int32_t *pi,
+                               const int32_t *pj, int64_t npairs, const double *h, double eta, double eps2,
+                               double G, int32_t *out)
+{
+    for (int64_t k = 0; k < npairs; ++k) {
+        const int i = pi[k], j = pj[k];
+        // the same rounded inputs the device edge test forms
+        const double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+        const double dvx = vx[i] - vx[j], dvy = vy[i] - vy[j], dvz = vz[i] - vz[j];
+        const double r2 = ((dx * dx + dy * dy) + dz * dz) + eps2;
+        const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
+        const double rv = (dx * dvx + dy * dvy) + dz * dvz;
+        const double mu = G * (m[i] + m[j]);
+        const ccs::Screen64 s = ccs::screen64_params(eta, h[k]);
+        out[k] = ccs::screen64(r2, v2, rv, mu, s);
+    }
+}
