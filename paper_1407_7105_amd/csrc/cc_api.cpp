@@ -55,17 +55,18 @@ struct Level {
     uint32_t *src = nullptr;
     Seg *pairs = nullptr;
     Seg *small[4] = {nullptr, nullptr, nullptr, nullptr};
-    Seg *big = nullptr;
-    int32_t *count = nullptr;    // 8 ints
-    int32_t *notstar = nullptr;  // cap_seg
-    Seg *seg = nullptr;
-    int32_t *offs = nullptr;     // 5 arrays of cap_seg+1: chunk, tile, act, kick prefixes, kick groups
-    // pinned host staging
-    Seg *h_seg = nullptr;
-    int32_t *h_offs = nullptr;
-    int32_t *h_count = nullptr;
-    Seg *h_big = nullptr;
-    int32_t *h_notstar = nullptr;
+    int32_t *notstar = nullptr;  // cap_seg: epoch of the visit that found the set not to be a star
+    // Report block, read back with one copy per visit: count[8] ([0] pairs,
+    // [1..4] small bins, [5] big, [7] error bits) followed by the big list.
+    int32_t *rep = nullptr, *h_rep = nullptr;
+    int32_t *count = nullptr, *h_count = nullptr;
+    Seg *big = nullptr, *h_big = nullptr;
+    // Descriptor block, uploaded with one copy per visit: nseg segments
+    // followed by 5 arrays of nseg+1 ints (chunk, tile, act, kick prefixes,
+    // kick groups).
+    unsigned char *desc = nullptr, *h_desc = nullptr;
+    Seg *seg = nullptr, *h_seg = nullptr;
+    int32_t *offs = nullptr, *h_offs = nullptr;
     int cap_big = 0, cap_small = 0, cap_pairs = 0;
 };
 
@@ -101,7 +102,8 @@ struct cc_ctx {
     uint64_t *h_stats = nullptr;
     int32_t *errf = nullptr;
     int32_t *h_err = nullptr;
-    int32_t *qhead = nullptr;
+    int32_t *qhead = nullptr;    // per level: work-queue head, then blocks finished
+    int32_t epoch = 0;           // visit counter for the non-star flags
     double *kick_acc = nullptr;  // 3*cap for cc_kick
     double *kick_part = nullptr; // partial accelerations of the tiled kick
     size_t kick_part_cap = 0;    // in kick blocks
@@ -247,25 +249,32 @@ int ensure_level(cc_ctx *c, int k, size_t nseg)
         RC(dalloc(c, &lv.labp, n));
         RC(dalloc(c, &lv.singp, n));
         RC(dalloc(c, &lv.src, n));
+        // top-level clusters of one particle also enter the small lists, so
+        // a list can hold up to n items
         lv.cap_pairs = (int)(n / 2 + 1);
-        lv.cap_small = (int)(n / 3 + 1);
+        lv.cap_small = (int)(n + 1);
         lv.cap_big = (int)(n / (size_t)(sm + 1) + 1);
         RC(dalloc(c, &lv.pairs, lv.cap_pairs));
         for (int b = 0; b < 4; ++b) RC(dalloc(c, &lv.small[b], lv.cap_small));
-        RC(dalloc(c, &lv.big, lv.cap_big));
-        RC(dalloc(c, &lv.count, 8));
-        RC(halloc(c, &lv.h_count, 8));
-        RC(halloc(c, &lv.h_big, lv.cap_big));
+        const size_t rep_ints = 8 + (size_t)lv.cap_big * (sizeof(Seg) / sizeof(int32_t));
+        RC(dalloc(c, &lv.rep, rep_ints));
+        RC(halloc(c, &lv.h_rep, rep_ints));
+        lv.count = lv.rep;
+        lv.h_count = lv.h_rep;
+        lv.big = reinterpret_cast<Seg *>(lv.rep + 8);
+        lv.h_big = reinterpret_cast<Seg *>(lv.h_rep + 8);
         lv.cap_n = n;
     }
     if (lv.cap_seg < nseg) {
         const size_t cs = std::max(nseg, (size_t)64);
         RC(dalloc(c, &lv.notstar, cs));
-        RC(dalloc(c, &lv.seg, cs));
-        RC(dalloc(c, &lv.offs, 5 * (cs + 1)));
-        RC(halloc(c, &lv.h_seg, cs));
-        RC(halloc(c, &lv.h_offs, 5 * (cs + 1)));
-        RC(halloc(c, &lv.h_notstar, cs));
+        // no stale flag may equal a later visit's epoch
+        HIPCHK(hipMemset(lv.notstar, 0, cs * sizeof(int32_t)));
+        const size_t bytes = cs * sizeof(Seg) + 5 * (cs + 1) * sizeof(int32_t);
+        RC(dalloc(c, &lv.desc, bytes));
+        RC(halloc(c, &lv.h_desc, bytes));
+        lv.seg = reinterpret_cast<Seg *>(lv.desc);
+        lv.h_seg = reinterpret_cast<Seg *>(lv.h_desc);
         lv.cap_seg = cs;
     }
     return CC_OK;
@@ -379,6 +388,26 @@ int err_code(cc_ctx *c, int bits)
     return CC_OK;
 }
 
+int32_t next_epoch(cc_ctx *c)
+{
+    if (++c->epoch <= 0) c->epoch = 1;
+    return c->epoch;
+}
+
+// The offset arrays follow the nseg segments in the descriptor block.
+void place_offsets(Level &lv, int nseg)
+{
+    lv.offs = reinterpret_cast<int32_t *>(lv.desc + (size_t)nseg * sizeof(Seg));
+    lv.h_offs = reinterpret_cast<int32_t *>(lv.h_desc + (size_t)nseg * sizeof(Seg));
+}
+
+int upload_desc(cc_ctx *c, Level &lv, int nseg)
+{
+    const size_t bytes = (size_t)nseg * sizeof(Seg) + 5 * ((size_t)nseg + 1) * sizeof(int32_t);
+    HIPCHK(hipMemcpyAsync(lv.desc, lv.h_desc, bytes, hipMemcpyHostToDevice, c->st));
+    return CC_OK;
+}
+
 // Work-queue heads are per level: the on-chip kernel of a level may still run
 // on the side stream while a deeper level launches its own on the main stream.
 int run_small_and_pairs(cc_ctx *c, int k, Level &lv, double H, int n_pairs, int n_small, hipStream_t st)
@@ -391,12 +420,12 @@ int run_small_and_pairs(cc_ctx *c, int k, Level &lv, double H, int n_pairs, int 
                             fam_ptr(c, F_PAIRS), st));
     }
     if (n_small > 0) {
-        HIPCHK(launch_fill_i32(c->qhead + k, 1, 0, st));
         SmallArgs sa{};
         for (int b = 0; b < 4; ++b) sa.bin[b] = lv.small[b];
         sa.count = lv.count + 1;
         sa.cap = lv.cap_small;
         sa.qhead = c->qhead + k;
+        sa.qdone = c->qhead + kLevels + k;
         const int sm = small_max(c);
         const size_t lds = small_lds_bytes(sm);
         int per_cu = (int)std::min<size_t>(8, std::max<size_t>(1, (160 * 1024) / (lds + 1024)));
@@ -460,6 +489,7 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
 
     // segment descriptors and prefix arrays
     const size_t S1 = (size_t)nseg + 1;
+    place_offsets(lv, nseg);
     int32_t *chunk = lv.h_offs, *tile = lv.h_offs + S1, *act = lv.h_offs + 2 * S1, *koff = lv.h_offs + 3 * S1,
             *kgrp = lv.h_offs + 4 * S1;
     chunk[0] = tile[0] = act[0] = koff[0] = 0;
@@ -481,17 +511,14 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         koff[s + 1] = (int32_t)nk;
         kgrp[s] = (int32_t)G;
     }
-    HIPCHK(hipMemcpyAsync(lv.seg, lv.h_seg, nseg * sizeof(Seg), hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipMemcpyAsync(lv.offs, lv.h_offs, 5 * S1 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+    RC(upload_desc(c, lv, nseg));
     GridLevelArgs a{lv.seg, lv.offs, lv.offs + S1, lv.offs + 2 * S1, lv.offs + 3 * S1, lv.offs + 4 * S1,
-                    nseg, chunk[nseg], tile[nseg], act[nseg], koff[nseg]};
+                    nseg, chunk[nseg], tile[nseg], act[nseg], koff[nseg], next_epoch(c)};
     const bool exact = exact_order(c);
     if (!exact && (size_t)a.nkblocks > c->kick_part_cap) {
         RC(dalloc(c, &c->kick_part, (size_t)a.nkblocks * 3 * TPB));
         c->kick_part_cap = a.nkblocks;
     }
-    HIPCHK(launch_fill_i32(lv.notstar, nseg, 0, c->st));
-    HIPCHK(launch_fill_i32(lv.count, 8, 0, c->st));
     {
         Span s(c, F_STAR);
         HIPCHK(launch_star(W, a, lv.notstar, c->parent, c->cnt, p, h, mixed(c), c->stats, fam_ptr(c, F_STAR), c->st));
@@ -502,8 +529,8 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     }
     {
         Span s(c, F_LABEL);
-        HIPCHK(launch_label(a, lv.notstar, c->parent, lv.label, c->cnt, c->stats, c->st));
-        HIPCHK(launch_keys(a, lv.label, c->keys, c->vals, c->st));
+        HIPCHK(launch_label(a, lv.notstar, c->parent, lv.label, c->cnt, c->keys, c->vals, lv.count, c->stats,
+                            c->st));
     }
     int bits = 0;
     {
@@ -529,15 +556,15 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     L.bin_lim[2] = 128;
     L.labp = exact ? nullptr : lv.labp;
     L.singp = exact ? nullptr : lv.singp;
+    L.errf = c->errf;
     {
         Span s(c, F_PERMUTE);
         HIPCHK(launch_permute(W, T, a, lv.src, lv.label, c->cnt, lv.sing, &L, c->stats, false, c->st));
     }
-    HIPCHK(hipMemcpyAsync(lv.h_count, lv.count, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipMemcpyAsync(lv.h_big, lv.big, lv.cap_big * sizeof(Seg), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(hipMemcpyAsync(c->h_err, c->errf, sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipMemcpyAsync(lv.h_rep, lv.rep, 8 * sizeof(int32_t) + (size_t)lv.cap_big * sizeof(Seg),
+                          hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
-    bits = *c->h_err;
+    bits = lv.h_count[7];
     if (bits) return err_code(c, bits);
     const int n_pairs = lv.h_count[0];
     const int n_small = lv.h_count[1] + lv.h_count[2] + lv.h_count[3] + lv.h_count[4];
@@ -566,13 +593,10 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
             HIPCHK(launch_drift_seg(W, a, lv2.singp, H, c->stats, c->st));
         }
         {
+            // the kick, then the second drift of the singletons (fused)
             Span s(c, F_KICK);
-            HIPCHK(launch_kick_tiles(W, a, lv2.labp, h, c->params.eps2, c->params.G, mixed(c), c->kick_part, c->errf,
-                                     c->stats, fam_ptr(c, F_KICK), c->st));
-        }
-        {
-            Span s(c, F_DRIFT);
-            HIPCHK(launch_drift_seg(W, a, lv2.singp, H, c->stats, c->st));
+            HIPCHK(launch_kick_tiles(W, a, lv2.labp, lv2.singp, h, c->params.eps2, c->params.G, mixed(c),
+                                     c->kick_part, c->errf, c->stats, fam_ptr(c, F_KICK), c->st));
         }
         if (any_sub) {
             RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
@@ -794,11 +818,15 @@ int cc_create(cc_ctx **out, int32_t hip_device, const cc_params *p)
         delete c;
         return CC_ERR_DEVICE;
     }
-    if (dalloc(c, &c->errf, 1) != CC_OK || halloc(c, &c->h_err, 1) != CC_OK || dalloc(c, &c->qhead, kLevels) != CC_OK ||
+    if (dalloc(c, &c->errf, 1) != CC_OK || halloc(c, &c->h_err, 1) != CC_OK || dalloc(c, &c->qhead, 2 * kLevels) != CC_OK ||
         dalloc(c, &c->diag_out, 16) != CC_OK || halloc(c, &c->h_diag, 16) != CC_OK ||
         dalloc(c, &c->fam_work, 2 * F_N) != CC_OK) {
         cc_destroy(c);
         return CC_ERR_OOM;
+    }
+    if (hipMemset(c->qhead, 0, 2 * kLevels * sizeof(int32_t)) != hipSuccess) {
+        cc_destroy(c);
+        return CC_ERR_DEVICE;
     }
     *out = c;
     return CC_OK;
@@ -825,8 +853,8 @@ void cc_destroy(cc_ctx *c)
     for (auto &lv : c->levels) {
         F(lv.label); F(lv.sing); F(lv.labp); F(lv.singp); F(lv.src); F(lv.pairs);
         for (auto *p : lv.small) F(p);
-        F(lv.big); F(lv.count); F(lv.notstar); F(lv.seg); F(lv.offs);
-        FH(lv.h_seg); FH(lv.h_offs); FH(lv.h_count); FH(lv.h_big); FH(lv.h_notstar);
+        F(lv.rep); F(lv.notstar); F(lv.desc);
+        FH(lv.h_rep); FH(lv.h_desc);
     }
     for (auto &r : c->recs) {
         hipEventDestroy(r.a);
@@ -886,18 +914,17 @@ int cc_split_labels(cc_ctx *c, const cc_state *s, int64_t n, double h, int32_t *
     if (T64 * (T64 + 1) / 2 > INT32_MAX) return fail(c, CC_ERR_ARG, "n too large");
     const int NT = (int)(T64 * (T64 + 1) / 2);
     lv.h_seg[0] = Seg{0, (int32_t)n, 0, 0};
+    place_offsets(lv, 1);
     int32_t *o = lv.h_offs;
     o[0] = 0; o[1] = T; o[2] = 0; o[3] = NT; o[4] = 0; o[5] = (int32_t)n;
-    HIPCHK(hipMemcpyAsync(lv.seg, lv.h_seg, sizeof(Seg), hipMemcpyHostToDevice, c->st));
-    HIPCHK(hipMemcpyAsync(lv.offs, lv.h_offs, 6 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
-    GridLevelArgs a{lv.seg, lv.offs, lv.offs + 2, lv.offs + 4, nullptr, nullptr, 1, T, NT, (int)n, 0};
+    RC(upload_desc(c, lv, 1));
+    GridLevelArgs a{lv.seg, lv.offs, lv.offs + 2, lv.offs + 4, nullptr, nullptr, 1, T, NT, (int)n, 0, next_epoch(c)};
     HIPCHK(hipMemsetAsync(c->stats, 0, ST_N * sizeof(uint64_t), c->st));
-    HIPCHK(launch_fill_i32(lv.notstar, 1, 0, c->st));
     const DevParams p = dev_params(c);
     SoA S = user_soa(s);
     HIPCHK(launch_star(S, a, lv.notstar, c->parent, c->cnt, p, h, mixed(c), c->stats, nullptr, c->st));
     HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, mixed(c), c->stats, nullptr, c->st));
-    HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, c->cnt, c->stats, c->st));
+    HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, c->cnt, nullptr, nullptr, nullptr, c->stats, c->st));
     if (n_nontrivial_out) {
         // roots carry their component size in cnt (zeroed for every slot by the star kernel)
         std::vector<int32_t> cnt((size_t)n);

@@ -213,9 +213,9 @@ __global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v)
 template <bool MIXED>
 __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg,
                                                const int32_t *__restrict__ chunk_off, int nseg,
-                                               int32_t *__restrict__ notstar, int32_t *__restrict__ parent,
-                                               int32_t *__restrict__ cnt, DevParams p, double h,
-                                               uint64_t *stats, uint64_t *fam)
+                                               int32_t *__restrict__ notstar, int32_t epoch,
+                                               int32_t *__restrict__ parent, int32_t *__restrict__ cnt,
+                                               DevParams p, double h, uint64_t *stats, uint64_t *fam)
 {
     __shared__ uint64_t sh[4];
     const int s = find_seg(chunk_off, nseg, blockIdx.x);
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg
             if (!edge_decide<MIXED>(S.x[X] - S.x[u], S.y[X] - S.y[u], S.z[X] - S.z[u], S.vx[X] - S.vx[u],
                                     S.vy[X] - S.vy[u], S.vz[X] - S.vz[u], S.m[X] + S.m[u], p,
                                     screen_params(p, h), ccs::screen64_params(p.eta, h), h))
-                notstar[s] = 1;
+                notstar[s] = epoch;
         }
     }
     const uint64_t t = block_sum_u64(ev, sh);
@@ -255,7 +255,7 @@ constexpr int ST = 64;  // sweep tile edge (one wavefront)
 template <bool MIXED>
 __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ seg,
                                                 const int32_t *__restrict__ tile_off, int nseg,
-                                                const int32_t *__restrict__ notstar,
+                                                const int32_t *__restrict__ notstar, int32_t epoch,
                                                 int32_t *__restrict__ parent, DevParams p, double h,
                                                 uint64_t *stats, uint64_t *fam)
 {
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
     bool active = tile < total;
     if (active) {
         s = find_seg(tile_off, nseg, tile);
-        active = notstar[s] != 0;
+        active = notstar[s] == epoch;
     }
     Seg g{0, 0, 0, 0};
     if (active) {
@@ -360,22 +360,34 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
     }
 }
 
-// Labels (smallest slot of the component) and component sizes.
+// Labels (smallest slot of the component) and component sizes.  With keys,
+// also the sort keys of the active particles (key = label, value = slot: a
+// stable sort by label makes every component contiguous, members in slot
+// order), and with `count` the level's work-list counters are cleared.
 __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, const int32_t *__restrict__ chunk_off,
-                                                int nseg, const int32_t *__restrict__ notstar,
+                                                const int32_t *__restrict__ act_off, int nseg,
+                                                const int32_t *__restrict__ notstar, int32_t epoch,
                                                 int32_t *__restrict__ parent, int32_t *__restrict__ label,
-                                                int32_t *__restrict__ cnt, uint64_t *stats)
+                                                int32_t *__restrict__ cnt, uint32_t *__restrict__ keys,
+                                                uint32_t *__restrict__ vals, int32_t *__restrict__ count,
+                                                uint64_t *stats)
 {
     const int s = find_seg(chunk_off, nseg, blockIdx.x);
     const Seg g = seg[s];
     const int local = (blockIdx.x - chunk_off[s]) * TPB + threadIdx.x;
-    const bool ns = notstar[s] != 0;
+    const bool ns = notstar[s] == epoch;
     const bool valid = local < g.n;
+    if (count && blockIdx.x == 0 && threadIdx.x < 8) count[threadIdx.x] = 0;
     int32_t l = -1;
     if (valid) {
         const int u = g.start + local;
         l = ns ? gfind(parent, u) : g.start;
         label[u] = l;
+        if (keys) {
+            const int k = act_off[s] + local;
+            keys[k] = (uint32_t)l;
+            vals[k] = (uint32_t)u;
+        }
     }
     // component sizes: one atomic per distinct label of the wavefront (a
     // large component fills whole wavefronts with one label)
@@ -394,19 +406,6 @@ __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, cons
         stat_add(stats, g.cluster, ST_SPLIT, 1);
         stat_max(stats, g.cluster, g.depth);
     }
-}
-
-// Sort keys: active index k -> slot; key = label (ascending label groups a
-// component, stable sort keeps members in slot order).
-__global__ void k_keys(const Seg *__restrict__ seg, const int32_t *__restrict__ act_off, int nseg, int nact,
-                       const int32_t *__restrict__ label, uint32_t *__restrict__ keys, uint32_t *__restrict__ vals)
-{
-    const int k = blockIdx.x * TPB + threadIdx.x;
-    if (k >= nact) return;
-    const int s = find_seg(act_off, nseg, k);
-    const int slot = seg[s].start + (k - act_off[s]);
-    keys[k] = (uint32_t)label[slot];
-    vals[k] = (uint32_t)slot;
 }
 
 struct Tmp {
@@ -457,6 +456,7 @@ struct Lists {
     int32_t bin_lim[3];  // upper sizes of bins 0..2 (bin 3 up to small_max)
     int32_t *labp;       // optional: label of the particle now at each slot
     uint8_t *singp;      // optional: singleton flag of the particle now at each slot
+    const int32_t *errf; // error bits, copied to count[7] for the host's one read-back
 };
 
 __global__ void k_scatter(SoA W, Tmp T, const Seg *__restrict__ seg, const int32_t *__restrict__ act_off,
@@ -482,6 +482,7 @@ __global__ void k_scatter(SoA W, Tmp T, const Seg *__restrict__ seg, const int32
     W.m[dst] = T.m[k];
     W.orig[dst] = T.orig[k];
     if (!with_lists) return;
+    if (k == 0) L.count[7] = __hip_atomic_load(L.errf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int32_t l = T.lab[k];
     if (L.labp) {
         L.labp[dst] = l;
@@ -671,29 +672,44 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
     }
 }
 
+// Adds the partial accelerations of every i in group order, applies the kick,
+// then the drift D_{hh} of the singletons that ends the level's D K D.
 __global__ __launch_bounds__(TPB) void k_kick_combine(SoA W, const Seg *__restrict__ seg,
                                                        const int32_t *__restrict__ chunk_off,
                                                        const int32_t *__restrict__ kick_off,
                                                        const int32_t *__restrict__ kgrp, int nseg,
-                                                       const double *__restrict__ part, double h)
+                                                       const double *__restrict__ part, double h,
+                                                       const uint8_t *__restrict__ sing, double hh,
+                                                       uint64_t *stats)
 {
+    __shared__ uint64_t sh[4];
     const int s = find_seg(chunk_off, nseg, blockIdx.x);
     const Seg g = seg[s];
     const int I = blockIdx.x - chunk_off[s];
     const int il = I * TPB + threadIdx.x;
-    if (il >= g.n) return;
-    const int Gs = kgrp[s];
-    const double *pb = part + (size_t)(kick_off[s] + I * Gs) * 3 * TPB;
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    for (int q = 0; q < Gs; ++q) {
-        ax += pb[(size_t)q * 3 * TPB + threadIdx.x];
-        ay += pb[(size_t)q * 3 * TPB + TPB + threadIdx.x];
-        az += pb[(size_t)q * 3 * TPB + 2 * TPB + threadIdx.x];
+    uint64_t drifted = 0;
+    if (il < g.n) {
+        const int Gs = kgrp[s];
+        const double *pb = part + (size_t)(kick_off[s] + I * Gs) * 3 * TPB;
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        for (int q = 0; q < Gs; ++q) {
+            ax += pb[(size_t)q * 3 * TPB + threadIdx.x];
+            ay += pb[(size_t)q * 3 * TPB + TPB + threadIdx.x];
+            az += pb[(size_t)q * 3 * TPB + 2 * TPB + threadIdx.x];
+        }
+        const int u = g.start + il;
+        W.vx[u] += h * ax;
+        W.vy[u] += h * ay;
+        W.vz[u] += h * az;
+        if (sing[u]) {
+            W.x[u] += hh * W.vx[u];
+            W.y[u] += hh * W.vy[u];
+            W.z[u] += hh * W.vz[u];
+            drifted = 1;
+        }
     }
-    const int u = g.start + il;
-    W.vx[u] += h * ax;
-    W.vy[u] += h * ay;
-    W.vz[u] += h * az;
+    const uint64_t t = block_sum_u64(drifted, sh);
+    if (threadIdx.x == 0) stat_add(stats, g.cluster, ST_DRIFT, t);
 }
 
 // Kick used by the cc_kick entry point: same sums, but velocities are written
@@ -1270,8 +1286,8 @@ struct SmallItems {
 };
 
 template <int CAP, int MODE>
-__global__ __launch_bounds__(TPB) void k_small(SoA W, SmallItems items, int32_t *qhead, double H, DevParams p,
-                                                int32_t *err, uint64_t *stats, uint64_t *fam)
+__global__ __launch_bounds__(TPB) void k_small(SoA W, SmallItems items, int32_t *qhead, int32_t *qdone, double H,
+                                                DevParams p, int32_t *err, uint64_t *stats, uint64_t *fam)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     SmallLDS<CAP> &L = *reinterpret_cast<SmallLDS<CAP> *>(smem_raw);
@@ -1308,6 +1324,15 @@ __global__ __launch_bounds__(TPB) void k_small(SoA W, SmallItems items, int32_t 
             continue;
         }
         SmallKernel<CAP, MODE>::run_item(W, L, g, H, p, err, stats, fam);
+    }
+    // The last block to leave resets the queue for the next launch on it (each
+    // block took its final, out-of-range ticket before counting itself out).
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(qdone, 1) == (int)gridDim.x - 1) {
+            atomicExch(qhead, 0);
+            atomicExch(qdone, 0);
+        }
     }
 }
 
@@ -1451,10 +1476,10 @@ hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t 
 {
     if (mixed)
         hipLaunchKernelGGL(k_star<true>, dim3(a.nchunks), dim3(TPB), 0, st, S, a.seg, a.chunk_off, a.nseg, notstar,
-                           parent, cnt, p, h, stats, fam);
+                           a.epoch, parent, cnt, p, h, stats, fam);
     else
         hipLaunchKernelGGL(k_star<false>, dim3(a.nchunks), dim3(TPB), 0, st, S, a.seg, a.chunk_off, a.nseg, notstar,
-                           parent, cnt, p, h, stats, fam);
+                           a.epoch, parent, cnt, p, h, stats, fam);
     return hipGetLastError();
 }
 
@@ -1464,26 +1489,19 @@ hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, i
     if (a.ntiles == 0) return hipSuccess;
     const int nb = (a.ntiles + TPB / ST - 1) / (TPB / ST);
     if (mixed)
-        hipLaunchKernelGGL(k_sweep<true>, dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar, parent,
-                           p, h, stats, fam);
+        hipLaunchKernelGGL(k_sweep<true>, dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar,
+                           a.epoch, parent, p, h, stats, fam);
     else
-        hipLaunchKernelGGL(k_sweep<false>, dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar, parent,
-                           p, h, stats, fam);
+        hipLaunchKernelGGL(k_sweep<false>, dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar,
+                           a.epoch, parent, p, h, stats, fam);
     return hipGetLastError();
 }
 
 hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,
-                        uint64_t *stats, hipStream_t st)
+                        uint32_t *keys, uint32_t *vals, int32_t *count, uint64_t *stats, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_label, dim3(a.nchunks), dim3(TPB), 0, st, a.seg, a.chunk_off, a.nseg, notstar, parent, label,
-                       cnt, stats);
-    return hipGetLastError();
-}
-
-hipError_t launch_keys(const GridLevelArgs &a, const int32_t *label, uint32_t *keys, uint32_t *vals, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_keys, dim3(nblocks(a.nact, 1 << 30)), dim3(TPB), 0, st, a.seg, a.act_off, a.nseg, a.nact,
-                       label, keys, vals);
+    hipLaunchKernelGGL(k_label, dim3(a.nchunks), dim3(TPB), 0, st, a.seg, a.chunk_off, a.act_off, a.nseg, notstar,
+                       a.epoch, parent, label, cnt, keys, vals, count, stats);
     return hipGetLastError();
 }
 
@@ -1532,6 +1550,7 @@ hipError_t launch_permute(SoA W, const TmpArrays &t, const GridLevelArgs &a, con
             for (int b = 0; b < 3; ++b) L.bin_lim[b] = lists->bin_lim[b];
             L.labp = lists->labp;
             L.singp = lists->singp;
+            L.errf = lists->errf;
         }
         hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(TPB), 0, st, W, T, a.seg, a.act_off, a.nseg, a.nact,
                            (const uint32_t *)nullptr, cnt, L, with, stats);
@@ -1562,8 +1581,9 @@ hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, 
     return hipGetLastError();
 }
 
-hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const int32_t *labp, double h, double eps2, double G,
-                             bool mixed, double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
+hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const int32_t *labp, const uint8_t *singp, double h,
+                             double eps2, double G, bool mixed, double *part, int32_t *err, uint64_t *stats,
+                             uint64_t *fam, hipStream_t st)
 {
     if (mixed)
         hipLaunchKernelGGL(k_kick_tiles<true>, dim3(a.nkblocks), dim3(TPB), 0, st, W, a.seg, a.kick_off, a.kgrp,
@@ -1572,7 +1592,7 @@ hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const int32_t *labp,
         hipLaunchKernelGGL(k_kick_tiles<false>, dim3(a.nkblocks), dim3(TPB), 0, st, W, a.seg, a.kick_off, a.kgrp,
                            a.nseg, labp, eps2, G, part, err, stats, fam);
     hipLaunchKernelGGL(k_kick_combine, dim3(a.nchunks), dim3(TPB), 0, st, W, a.seg, a.chunk_off, a.kick_off, a.kgrp,
-                       a.nseg, (const double *)part, h);
+                       a.nseg, (const double *)part, h, singp, 0.5 * h, stats);
     return hipGetLastError();
 }
 
@@ -1619,7 +1639,8 @@ static hipError_t launch_small_cap(SoA W, const SmallArgs &s, double H, DevParam
     for (int b = 0; b < 4; ++b) it.bin[b] = s.bin[b];
     it.count = s.count;
     it.cap = s.cap;
-    hipLaunchKernelGGL((k_small<CAP, MODE>), dim3(nblk), dim3(TPB), lds, st, W, it, s.qhead, H, p, err, stats, fam);
+    hipLaunchKernelGGL((k_small<CAP, MODE>), dim3(nblk), dim3(TPB), lds, st, W, it, s.qhead, s.qdone, H, p, err, stats,
+                       fam);
     return hipGetLastError();
 }
 

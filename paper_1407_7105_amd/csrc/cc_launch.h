@@ -18,6 +18,7 @@ struct GridLevelArgs {
     const int32_t *kick_off;   // prefix over kick blocks (i tiles x j groups), nseg+1
     const int32_t *kgrp;       // j groups per segment, nseg
     int nseg, nchunks, ntiles, nact, nkblocks;
+    int32_t epoch;             // marks this visit's non-star flags (no clearing between visits)
 };
 
 struct TmpArrays {
@@ -35,13 +36,15 @@ struct ListArgs {
     int32_t bin_lim[3];
     int32_t *labp;   // optional permuted-order labels
     uint8_t *singp;  // optional permuted-order singleton flags
+    const int32_t *errf;  // error bits, snapshot into count[7]
 };
 
 struct SmallArgs {
     const Seg *bin[4];
     const int32_t *count;  // 4 bin counts
     int32_t cap;
-    int32_t *qhead;
+    int32_t *qhead;  // work-queue head, 0 before a launch; the launch's last block resets it
+    int32_t *qdone;  // blocks finished, likewise reset
 };
 
 hipError_t launch_validate(const double *x, const double *y, const double *z, const double *vx, const double *vy,
@@ -56,9 +59,10 @@ hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t 
                        double h, bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st);
 hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, DevParams p, double h,
                         bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st);
+// labels and component sizes; with keys/vals the sort keys of the active
+// particles, with count the work-list counters cleared
 hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,
-                        uint64_t *stats, hipStream_t st);
-hipError_t launch_keys(const GridLevelArgs &a, const int32_t *label, uint32_t *keys, uint32_t *vals, hipStream_t st);
+                        uint32_t *keys, uint32_t *vals, int32_t *count, uint64_t *stats, hipStream_t st);
 size_t sort_temp_bytes(int n);
 hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, uint32_t *keys_out,
                        const uint32_t *vals_in, uint32_t *vals_out, int n, int end_bit, hipStream_t st);
@@ -72,8 +76,10 @@ hipError_t launch_drift_seg(SoA W, const GridLevelArgs &a, const uint8_t *sing, 
                             hipStream_t st);
 hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, double h, double eps2, double G,
                            int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
-hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const int32_t *labp, double h, double eps2, double G,
-                             bool mixed, double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
+// kick K_h of the level, then the drift D_{h/2} of its singletons (singp)
+hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const int32_t *labp, const uint8_t *singp, double h,
+                             double eps2, double G, bool mixed, double *part, int32_t *err, uint64_t *stats,
+                             uint64_t *fam, hipStream_t st);
 hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, double *ax, double *ay,
                            double *az, int32_t *err, hipStream_t st);
 hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, const double *az, double h,
