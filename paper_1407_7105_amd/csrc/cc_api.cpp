@@ -501,7 +501,9 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         lv.h_seg[s] = segs[s];
         const int n = segs[s].n;
         const int64_t T = (n + TPB - 1) / TPB;
-        const int64_t G = std::min<int64_t>(T, gtarget);
+        // j groups of at least 32 partners: small sets get short, parallel
+        // partner loops instead of one long one
+        const int64_t G = std::min<int64_t>((n + 31) / 32, gtarget);
         const int64_t T64 = (n + SWEEP_TILE - 1) / SWEEP_TILE;
         const int64_t nt = tile[s] + T64 * (T64 + 1) / 2, nk = koff[s] + T * G;
         if (nt > INT32_MAX || nk > INT32_MAX) return fail(c, CC_ERR_ARG, "set of %d particles is too large", n);

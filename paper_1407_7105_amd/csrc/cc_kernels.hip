@@ -251,20 +251,30 @@ __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg
 // particle whose local root has a different global root into the global
 // structure: at most one global union per particle per tile.
 constexpr int ST = 64;  // sweep tile edge (one wavefront)
+constexpr int SWEEP_SPLIT_TILES = 2048;  // launches up to this many tiles use one block per tile
 
-template <bool MIXED>
+// One ST x ST tile of a set's pair triangle per JS wavefronts: wavefront
+// jpart of the tile takes the tile's i particles against its ST/JS partners
+// (JS = 1 for large launches; JS > 1 shortens the partner loop when a launch
+// has few tiles).  The tile's edges are first linked in an LDS union-find over
+// its 2 ST particles, then merged into the global structure.
+template <bool MIXED, int JS>
 __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ seg,
                                                 const int32_t *__restrict__ tile_off, int nseg,
                                                 const int32_t *__restrict__ notstar, int32_t epoch,
                                                 int32_t *__restrict__ parent, DevParams p, double h,
                                                 uint64_t *stats, uint64_t *fam)
 {
-    constexpr int NW = TPB / ST;
-    __shared__ double jx[NW][ST], jy[NW][ST], jz[NW][ST], jvx[NW][ST], jvy[NW][ST], jvz[NW][ST], jm[NW][ST];
-    __shared__ int32_t lpar[NW][2 * ST];
-    __shared__ int32_t groot[NW][2 * ST];
+    constexpr int NW = TPB / ST;   // wavefronts per block
+    constexpr int TPW = NW / JS;   // tiles per block
+    constexpr int JW = ST / JS;    // partners per wavefront
+    static_assert(NW % JS == 0, "JS must divide the wavefronts of a block");
+    __shared__ double jx[NW][JW], jy[NW][JW], jz[NW][JW], jvx[NW][JW], jvy[NW][JW], jvz[NW][JW], jm[NW][JW];
+    __shared__ int32_t lpar[TPW][2 * ST];
+    __shared__ int32_t groot[TPW][2 * ST];
     const int w = threadIdx.x / ST, lane = threadIdx.x % ST;
-    const int tile = blockIdx.x * NW + w;
+    const int ts = w / JS, jpart = w % JS;
+    const int tile = blockIdx.x * TPW + ts;
     const int total = tile_off[nseg];
     int s = 0, ti = 0, tj = 0, T = 0;
     bool active = tile < total;
@@ -285,25 +295,32 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
     }
     const bool diag = (ti == tj);
     const int jn = active ? min(ST, g.n - tj * ST) : 0;
+    const int j0w = jpart * JW;                      // first partner of this wavefront within the tile
+    const int jnw = max(0, min(JW, jn - j0w));       // partners of this wavefront
     const int il = ti * ST + lane;
     const bool ivalid = active && il < g.n;
     const int i = g.start + (ivalid ? il : 0);
-    int32_t *lp = lpar[w];
-    int32_t *gr = groot[w];
-    lp[lane] = lane;
-    lp[ST + lane] = ST + lane;
-    gr[lane] = ivalid ? gfind(parent, i) : -1;
-    gr[ST + lane] = -1;
-    if (lane < jn) {
-        const int j = g.start + tj * ST + lane;
-        jx[w][lane] = S.x[j];
-        jy[w][lane] = S.y[j];
-        jz[w][lane] = S.z[j];
-        jvx[w][lane] = S.vx[j];
-        jvy[w][lane] = S.vy[j];
-        jvz[w][lane] = S.vz[j];
-        jm[w][lane] = S.m[j];
-        if (!diag) gr[ST + lane] = gfind(parent, j);
+    int32_t *lp = lpar[ts];
+    int32_t *gr = groot[ts];
+    if (jpart == 0) {
+        lp[lane] = lane;
+        gr[lane] = ivalid ? gfind(parent, i) : -1;
+    }
+    if (lane < JW) {
+        const int v = ST + j0w + lane;
+        lp[v] = v;
+        gr[v] = -1;
+        if (lane < jnw) {
+            const int j = g.start + tj * ST + j0w + lane;
+            jx[w][lane] = S.x[j];
+            jy[w][lane] = S.y[j];
+            jz[w][lane] = S.z[j];
+            jvx[w][lane] = S.vx[j];
+            jvy[w][lane] = S.vy[j];
+            jvz[w][lane] = S.vz[j];
+            jm[w][lane] = S.m[j];
+            if (!diag) gr[v] = gfind(parent, j);
+        }
     }
     __syncthreads();
     uint64_t ev = 0;
@@ -312,11 +329,11 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
         const double vxi = S.vx[i], vyi = S.vy[i], vzi = S.vz[i], mi = S.m[i];
         const ScreenParams q = screen_params(p, h);
         const ccs::Screen64 s64 = ccs::screen64_params(p.eta, h);
-        // Decide every pair of the tile first (one bit per partner: edge, or
-        // left to the literal formula), with a loop that is uniform across
-        // the wavefront; then resolve the undecided pairs and link the edges.
+        // Decide every pair first (one bit per partner: edge, or left to the
+        // literal formula), with a loop that is uniform across the
+        // wavefront; then resolve the undecided pairs and link the edges.
         uint64_t emask = 0, umask = 0;
-        for (int jj = 0; jj < jn; ++jj) {
+        for (int jj = 0; jj < jnw; ++jj) {
             const int d = edge_screen<MIXED>(xi - jx[w][jj], yi - jy[w][jj], zi - jz[w][jj], vxi - jvx[w][jj],
                                              vyi - jvy[w][jj], vzi - jvz[w][jj], mi + jm[w][jj], p, q, s64);
             const uint64_t bit = 1ull << jj;
@@ -324,11 +341,11 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
             umask |= (d == ccs::SCREEN64_UNSURE) ? bit : 0ull;
         }
         // partners of this lane: j > i on the diagonal tile, all j otherwise
-        const uint64_t keep = !ivalid ? 0ull : !diag ? ~0ull : (lane >= ST - 1) ? 0ull : (~0ull << (lane + 1));
+        const int sh = lane + 1 - j0w;  // first partner bit with j > i
+        const uint64_t keep = !ivalid ? 0ull : (!diag || sh <= 0) ? ~0ull : (sh >= 64) ? 0ull : (~0ull << sh);
         emask &= keep;
         umask &= keep;
-        const int j0 = diag ? lane + 1 : 0;
-        ev = (ivalid && jn > j0) ? (uint64_t)(jn - j0) : 0;
+        ev = !ivalid ? 0 : (uint64_t)(diag ? max(0, jnw - max(0, sh)) : jnw);
         while (umask) {
             const int jj = __builtin_ctzll(umask);
             umask &= umask - 1;
@@ -338,7 +355,7 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
         }
         const int32_t gi = gr[lane];
         int32_t lr = lane;  // an ancestor of this particle in the local structure
-        const int joff = diag ? 0 : ST;
+        const int joff = (diag ? 0 : ST) + j0w;
         while (emask) {
             const int jj = __builtin_ctzll(emask);
             emask &= emask - 1;
@@ -348,7 +365,7 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
     }
     __syncthreads();
     // merge the tile's local sets into the global structure
-    for (int v = lane; v < 2 * ST; v += ST) {
+    for (int v = jpart * ST + lane; v < 2 * ST; v += JS * ST) {
         if (gr[v] < 0) continue;
         const int r = lfind(lp, v);
         if (r != v && gr[r] != gr[v]) gunite(parent, gr[v], gr[r]);
@@ -593,6 +610,8 @@ __global__ __launch_bounds__(TPB) void k_kick_seg(SoA W, const Seg *__restrict__
 // skipped whole (all its pairs are inside one component).  Each block writes
 // its partial accelerations; k_kick_combine adds the groups of every i in
 // group order, so the result is deterministic.
+constexpr int KICK_JW = 32;  // granularity of the j ranges of the kick groups
+
 template <bool MIXED>
 __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict__ seg,
                                                      const int32_t *__restrict__ kick_off,
@@ -606,12 +625,12 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
     __shared__ uint64_t sh[4];
     const int s = find_seg(kick_off, nseg, blockIdx.x);
     const Seg g = seg[s];
-    const int T = (g.n + TPB - 1) / TPB;
     const int Gs = kgrp[s];
     const int local = blockIdx.x - kick_off[s];
     const int I = local / Gs, grp = local % Gs;
-    const int per = (T + Gs - 1) / Gs;
-    const int t0 = grp * per, t1 = min(T, t0 + per);
+    // j range of this group: Gs equal ranges, multiples of KICK_JW partners
+    const int jw = (((g.n + Gs - 1) / Gs) + KICK_JW - 1) / KICK_JW * KICK_JW;
+    const int jlo = min(g.n, grp * jw), jhi = min(g.n, jlo + jw);
     const int il = I * TPB + threadIdx.x;
     const bool valid = il < g.n;
     const int i = g.start + (valid ? il : 0);
@@ -622,9 +641,8 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
     double ax = 0.0, ay = 0.0, az = 0.0;
     uint64_t pairs = 0;
     bool ok = true;
-    for (int t = t0; t < t1; ++t) {
-        const int jb = t * TPB;
-        const int jn = min(TPB, g.n - jb);
+    for (int jb = jlo; jb < jhi; jb += TPB) {
+        const int jn = min(TPB, jhi - jb);
         const int jfirst = g.start + jb, jlast = g.start + jb + jn - 1;
         if (iu >= 0 && labp[jfirst] == iu && labp[jlast] == iu) continue;  // uniform across the block
         __syncthreads();
@@ -1487,13 +1505,25 @@ hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, i
                         bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
     if (a.ntiles == 0) return hipSuccess;
-    const int nb = (a.ntiles + TPB / ST - 1) / (TPB / ST);
-    if (mixed)
-        hipLaunchKernelGGL(k_sweep<true>, dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar,
-                           a.epoch, parent, p, h, stats, fam);
-    else
-        hipLaunchKernelGGL(k_sweep<false>, dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar,
-                           a.epoch, parent, p, h, stats, fam);
+    // launches of few tiles give each tile a whole block (4 wavefronts of
+    // 16 partners each) so the partner loops are short
+    const bool split = a.ntiles <= SWEEP_SPLIT_TILES;
+    const int nb = split ? a.ntiles : (a.ntiles + TPB / ST - 1) / (TPB / ST);
+    if (mixed) {
+        if (split)
+            hipLaunchKernelGGL((k_sweep<true, 4>), dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar,
+                               a.epoch, parent, p, h, stats, fam);
+        else
+            hipLaunchKernelGGL((k_sweep<true, 1>), dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar,
+                               a.epoch, parent, p, h, stats, fam);
+    } else {
+        if (split)
+            hipLaunchKernelGGL((k_sweep<false, 4>), dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg,
+                               notstar, a.epoch, parent, p, h, stats, fam);
+        else
+            hipLaunchKernelGGL((k_sweep<false, 1>), dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg,
+                               notstar, a.epoch, parent, p, h, stats, fam);
+    }
     return hipGetLastError();
 }
 
