@@ -82,7 +82,7 @@ struct cc_ctx {
     cc_params params{};
     std::string err;
     hipStream_t st = nullptr;
-    hipStream_t side = nullptr;            // second stream: small/pair components overlap the grid recursion
+    hipStream_t side = nullptr;  // default priority: a level's on-chip components beside the recursion
     std::vector<hipEvent_t> sync_pool;     // ordering events (no timing)
     std::vector<hipEvent_t> sync_used;
     int cus = 256;
@@ -102,7 +102,7 @@ struct cc_ctx {
     uint64_t *h_stats = nullptr;
     int32_t *errf = nullptr;
     int32_t *h_err = nullptr;
-    int32_t *qhead = nullptr;    // per level: work-queue head, then blocks finished
+    int32_t *qhead = nullptr;    // per level: head and blocks finished of the workgroup and the wavefront queues
     int32_t epoch = 0;           // visit counter for the non-star flags
     double *kick_acc = nullptr;  // 3*cap for cc_kick
     double *kick_part = nullptr; // partial accelerations of the tiled kick
@@ -327,17 +327,25 @@ struct Span {
     }
 };
 
+// An ordering event (no timing) from the pool; returned to it once both
+// streams have been synchronised.
+int take_event(cc_ctx *c, hipEvent_t *e)
+{
+    if (!c->sync_pool.empty()) {
+        *e = c->sync_pool.back();
+        c->sync_pool.pop_back();
+    } else {
+        HIPCHK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    }
+    c->sync_used.push_back(*e);
+    return CC_OK;
+}
+
 // An ordering event recorded on `from`; `to` waits for it.
 int order_streams(cc_ctx *c, hipStream_t from, hipStream_t to)
 {
     hipEvent_t e;
-    if (!c->sync_pool.empty()) {
-        e = c->sync_pool.back();
-        c->sync_pool.pop_back();
-    } else {
-        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    }
-    c->sync_used.push_back(e);
+    RC(take_event(c, &e));
     HIPCHK(hipEventRecord(e, from));
     HIPCHK(hipStreamWaitEvent(to, e, 0));
     return CC_OK;
@@ -408,45 +416,47 @@ int upload_desc(cc_ctx *c, Level &lv, int nseg)
     return CC_OK;
 }
 
-// Work-queue heads are per level: the on-chip kernel of a level may still run
-// on the side stream while a deeper level launches its own on the main stream.
-int run_small_and_pairs(cc_ctx *c, int k, Level &lv, double H, int n_pairs, int n_small, hipStream_t st)
+// A level's two-particle and small components in one launch.  Queue
+// counters are per level: the launch of a level may still run on the side
+// stream while a deeper level launches its own.  n_small[b] = items in size
+// bin b.
+int run_small_and_pairs(cc_ctx *c, int k, Level &lv, double H, int n_pairs, const int n_small[4], hipStream_t st)
 {
+    const int n_block_items = n_small[2] + n_small[3];
+    const int n_wave_items = n_small[0] + n_small[1];
+    if (n_pairs + n_block_items + n_wave_items == 0) return CC_OK;
     const DevParams p = dev_params(c);
     SoA W = work_soa(c);
-    if (n_pairs > 0) {
-        Span s(c, F_PAIRS, st);
-        HIPCHK(launch_pairs(W, lv.pairs, lv.count, lv.cap_pairs, n_pairs, H, p, mixed(c), c->errf, c->stats,
-                            fam_ptr(c, F_PAIRS), st));
-    }
-    if (n_small > 0) {
-        SmallArgs sa{};
-        for (int b = 0; b < 4; ++b) sa.bin[b] = lv.small[b];
-        sa.count = lv.count + 1;
-        sa.cap = lv.cap_small;
-        sa.qhead = c->qhead + k;
-        sa.qdone = c->qhead + kLevels + k;
-        const int sm = small_max(c);
-        const size_t lds = small_lds_bytes(sm);
-        int per_cu = (int)std::min<size_t>(8, std::max<size_t>(1, (160 * 1024) / (lds + 1024)));
-        const int nblk = std::min(n_small, c->cus * per_cu);
-        Span s(c, F_SMALL, st);
-        HIPCHK(launch_small(W, sa, sm, mixed(c) ? 2 : (exact_order(c) ? 1 : 0), H, p, c->errf, c->stats,
-                            fam_ptr(c, F_SMALL), nblk, st));
-    }
+    SmallArgs sa{};
+    sa.pairs = lv.pairs;
+    for (int b = 0; b < 4; ++b) sa.bin[b] = lv.small[b];
+    sa.count = lv.count;
+    sa.cap = lv.cap_small;
+    sa.cap_pairs = lv.cap_pairs;
+    sa.queue = c->qhead + 4 * k;
+    const int sm = small_max(c);
+    const int per_cu = (int)std::min<size_t>(8, std::max<size_t>(1, (160 * 1024) / (items_lds_bytes(sm) + 1024)));
+    const int nbp = (n_pairs + TPB - 1) / TPB;
+    const int nbb = std::min(n_block_items, c->cus * per_cu);
+    const int nbw = std::min((n_wave_items + TPB / 64 - 1) / (TPB / 64), c->cus * per_cu);
+    Span s(c, F_SMALL, st);
+    HIPCHK(launch_items(W, sa, sm, mixed(c) ? 2 : (exact_order(c) ? 1 : 0), nbp, nbb, nbw, H, p, c->errf, c->stats,
+                        fam_ptr(c, F_SMALL), st));
     return CC_OK;
 }
 
 int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h);
 
 // Items of one list of independent sets at level depth: route by size.
-// The small and two-particle components of a level and its large components
-// are disjoint sets: the former run on the side stream while the host drives
-// the recursion into the latter on the main stream; the main stream waits for
-// the side stream before the level's own kick.
-int dispatch_sets(cc_ctx *c, int k, Level &lv, double H, const std::vector<Seg> &big, int n_pairs, int n_small)
+// The on-chip components of a level and its large components are disjoint
+// sets: the former run on the side stream while the host drives the recursion
+// into the latter on the main stream; the main stream waits for the side
+// stream before the level's own kick.
+int dispatch_sets(cc_ctx *c, int k, Level &lv, double H, const std::vector<Seg> &big, int n_pairs,
+                  const int n_small[4])
 {
-    if (big.empty() || n_pairs + n_small == 0) {
+    const bool on_chip = n_pairs + n_small[0] + n_small[1] + n_small[2] + n_small[3] > 0;
+    if (!on_chip || big.empty()) {
         RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, c->st));
         if (!big.empty()) RC(evolve_grid(c, k + 1, big, H));
         return CC_OK;
@@ -454,13 +464,7 @@ int dispatch_sets(cc_ctx *c, int k, Level &lv, double H, const std::vector<Seg> 
     RC(order_streams(c, c->st, c->side));
     RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, c->side));
     hipEvent_t done;
-    if (!c->sync_pool.empty()) {
-        done = c->sync_pool.back();
-        c->sync_pool.pop_back();
-    } else {
-        HIPCHK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-    }
-    c->sync_used.push_back(done);
+    RC(take_event(c, &done));
     HIPCHK(hipEventRecord(done, c->side));
     RC(evolve_grid(c, k + 1, big, H));
     HIPCHK(hipStreamWaitEvent(c->st, done, 0));
@@ -569,14 +573,14 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     bits = lv.h_count[7];
     if (bits) return err_code(c, bits);
     const int n_pairs = lv.h_count[0];
-    const int n_small = lv.h_count[1] + lv.h_count[2] + lv.h_count[3] + lv.h_count[4];
+    const int n_small[4] = {lv.h_count[1], lv.h_count[2], lv.h_count[3], lv.h_count[4]};
     const int n_big = lv.h_count[5];
     if (n_pairs > lv.cap_pairs || lv.h_count[1] > lv.cap_small || lv.h_count[2] > lv.cap_small ||
         lv.h_count[3] > lv.cap_small || lv.h_count[4] > lv.cap_small || n_big > lv.cap_big)
         return fail(c, CC_ERR_DEVICE, "internal work-list capacity exceeded");
     std::vector<Seg> big(lv.h_big, lv.h_big + n_big);
     std::sort(big.begin(), big.end(), [](const Seg &x, const Seg &y) { return x.start < y.start; });
-    const bool any_sub = (n_pairs + n_small + n_big) > 0;
+    const bool any_sub = (n_pairs + n_small[0] + n_small[1] + n_small[2] + n_small[3] + n_big) > 0;
     const double H = 0.5 * h;
     if (trace_on()) {
         int nmax = 0;
@@ -678,7 +682,7 @@ int global_step(cc_ctx *c, const std::vector<Seg> &top, double dt)
             if (!small[b].empty())
                 HIPCHK(hipMemcpyAsync(lv.small[b], small[b].data(), small[b].size() * sizeof(Seg),
                                       hipMemcpyHostToDevice, c->st));
-        const int ns = (int)(small[0].size() + small[1].size() + small[2].size() + small[3].size());
+        const int ns[4] = {(int)small[0].size(), (int)small[1].size(), (int)small[2].size(), (int)small[3].size()};
         RC(run_small_and_pairs(c, k, lv, dt, (int)pairs.size(), ns, c->st));
         // the host vectors must outlive the async copies
         HIPCHK(hipStreamSynchronize(c->st));
@@ -820,13 +824,13 @@ int cc_create(cc_ctx **out, int32_t hip_device, const cc_params *p)
         delete c;
         return CC_ERR_DEVICE;
     }
-    if (dalloc(c, &c->errf, 1) != CC_OK || halloc(c, &c->h_err, 1) != CC_OK || dalloc(c, &c->qhead, 2 * kLevels) != CC_OK ||
+    if (dalloc(c, &c->errf, 1) != CC_OK || halloc(c, &c->h_err, 1) != CC_OK || dalloc(c, &c->qhead, 4 * kLevels) != CC_OK ||
         dalloc(c, &c->diag_out, 16) != CC_OK || halloc(c, &c->h_diag, 16) != CC_OK ||
         dalloc(c, &c->fam_work, 2 * F_N) != CC_OK) {
         cc_destroy(c);
         return CC_ERR_OOM;
     }
-    if (hipMemset(c->qhead, 0, 2 * kLevels * sizeof(int32_t)) != hipSuccess) {
+    if (hipMemset(c->qhead, 0, 4 * kLevels * sizeof(int32_t)) != hipSuccess) {
         cc_destroy(c);
         return CC_ERR_DEVICE;
     }

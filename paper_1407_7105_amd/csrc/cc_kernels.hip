@@ -787,13 +787,13 @@ __global__ void k_apply_kick(SoA W, int n, const double *__restrict__ ax, const 
 // ---------------------------------------------------------------------------
 // Two-particle components, one per lane.
 // ---------------------------------------------------------------------------
+// Two-particle components, one per thread: threads t0, t0 + nt, ... of the
+// caller take items t0, t0 + nt, ...
 template <bool MIXED>
-__global__ __launch_bounds__(TPB) void k_pairs(SoA W, const Seg *__restrict__ items, const int32_t *__restrict__ count,
-                                                int cap, double H, DevParams p, int32_t *err, uint64_t *stats,
-                                                uint64_t *fam)
+__device__ void run_pairs(SoA W, const Seg *__restrict__ items, int n, int t0, int nt, double H, const DevParams &p,
+                          int32_t *err, uint64_t *stats, uint64_t *fam)
 {
-    const int n = min(count[0], cap);
-    for (int it = blockIdx.x * TPB + threadIdx.x; it < n; it += gridDim.x * TPB) {
+    for (int it = t0; it < n; it += nt) {
         const Seg g = items[it];
         int ia = g.start, ib = g.start + 1;
         if (W.orig[ib] < W.orig[ia]) {
@@ -832,6 +832,7 @@ __global__ __launch_bounds__(TPB) void k_pairs(SoA W, const Seg *__restrict__ it
 // together, which is exact because they share no particles.
 // ---------------------------------------------------------------------------
 constexpr int MAXL = 64;
+constexpr int SMALL_WAVE_CAP = 32;  // items of bins 0-1 (up to 32 particles) run one per wavefront
 
 template <int CAP>
 struct SmallLDS {
@@ -860,12 +861,27 @@ struct SmallLDS {
 
 // MODE: 0 = FP64, partners in slot order; 1 = FP64, partners in ascending
 // particle index (bit-identical to a sequential sweep); 2 = mixed precision.
-template <int CAP, int MODE>
+template <int CAP, int MODE, int NT>
 struct SmallKernel {
     static constexpr bool EXACT = (MODE == 1);
     static constexpr bool MIXED = (MODE == 2);
-    static constexpr int E = CAP / TPB;  // positions per thread
-    static constexpr int W = CAP / 32;   // mask words
+    static constexpr int E = (CAP + NT - 1) / NT;  // positions per thread
+    static constexpr int W = (CAP + 31) / 32;      // mask words
+    static_assert(NT == TPB || NT == WAVE, "a team is a workgroup or one wavefront");
+
+    // thread index within the team, and the team's barrier
+    static __device__ __forceinline__ int tid() { return (int)(threadIdx.x % NT); }
+    static __device__ __forceinline__ void sync()
+    {
+        if (NT == TPB) {
+            __syncthreads();
+        } else {
+            // one wavefront: order its LDS accesses around a wave-level barrier
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        }
+    }
 
     // Mask word of level-k segment starts: L_k = non-trivial components of level k-1.
     static __device__ __forceinline__ uint32_t start_word(const SmallLDS<CAP> &L, int k, int wi, int n)
@@ -893,9 +909,9 @@ struct SmallKernel {
     // two-particle sets.
     static __device__ void enumerate(SmallLDS<CAP> &L, int k, int n, bool collect_bins)
     {
-        if (threadIdx.x == 0) L.nbin = 0;
-        __syncthreads();
-        for (int p = threadIdx.x; p < n; p += TPB) {
+        if (tid() == 0) L.nbin = 0;
+        sync();
+        for (int p = tid(); p < n; p += NT) {
             const bool inL = (k == 0) || bit_of(L.nt[k - 1], p);
             if (!inL) {
                 L.segS[p] = -1;
@@ -926,7 +942,7 @@ struct SmallKernel {
                 L.binlist[i] = (int16_t)s;
             }
         }
-        __syncthreads();
+        sync();
     }
 
     static __device__ void count(SmallLDS<CAP> &L, int idx, unsigned long long v)
@@ -938,7 +954,7 @@ struct SmallKernel {
     {
         const int nb = L.nbin;
         PairCounters c{0, 0, 0, 0, 0, -1};
-        for (int i = threadIdx.x; i < nb; i += TPB) {
+        for (int i = tid(); i < nb; i += NT) {
             int ia = L.binlist[i], ib = ia + 1;
             if (L.orig[ib] < L.orig[ia]) {
                 const int t = ia;
@@ -959,7 +975,7 @@ struct SmallKernel {
         count(L, ST_COMP, c.comp);
         count(L, ST_SPLIT, c.split);
         if (c.maxd >= 0) atomicMax(&L.maxd, c.maxd);
-        __syncthreads();
+        sync();
     }
 
     // Exclusive prefix sum of cnt[0..CAP) into par[].
@@ -969,25 +985,27 @@ struct SmallKernel {
         int tot = 0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            v[e] = L.cnt[threadIdx.x * E + e];
+            const int q = tid() * E + e;
+            v[e] = q < CAP ? L.cnt[q] : 0;
             tot += v[e];
         }
         int incl = tot;
-        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int lane = tid() & 63, w = tid() >> 6;
         for (int o = 1; o < 64; o <<= 1) {
             const int t = __shfl_up(incl, o, 64);
             if (lane >= o) incl += t;
         }
         if (lane == 63) L.wsum[w] = incl;
-        __syncthreads();
+        sync();
         int before = incl - tot;
         for (int q = 0; q < w; ++q) before += L.wsum[q];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            L.par[threadIdx.x * E + e] = before;
+            const int q = tid() * E + e;
+            if (q < CAP) L.par[q] = before;
             before += v[e];
         }
-        __syncthreads();
+        sync();
     }
 
     static __device__ __forceinline__ bool is_main(const SmallLDS<CAP> &L, int p)
@@ -999,18 +1017,18 @@ struct SmallKernel {
     // Split every main set of L_k at h (eq. 20) and reorder it by component.
     static __device__ void split(SmallLDS<CAP> &L, int k, int n, double h, const DevParams &p)
     {
-        for (int w = threadIdx.x; w < W; w += TPB) {
+        for (int w = tid(); w < W; w += NT) {
             L.flag[w] = 0;
             L.cs[k][w] = 0;
             L.nt[k][w] = 0;
         }
-        for (int q = threadIdx.x; q < CAP; q += TPB) L.cnt[q] = 0;
-        __syncthreads();
+        for (int q = tid(); q < CAP; q += NT) L.cnt[q] = 0;
+        sync();
         unsigned long long tau = 0;
         const ScreenParams sq = screen_params(p, h);
         const ccs::Screen64 s64 = ccs::screen64_params(p.eta, h);
         // star test from each set's first position X
-        for (int q = threadIdx.x; q < n; q += TPB) {
+        for (int q = tid(); q < n; q += NT) {
             if (!is_main(L, q)) continue;
             L.par[q] = q;
             const int X = L.segS[q];
@@ -1020,9 +1038,9 @@ struct SmallKernel {
                                     L.vy[X] - L.vy[q], L.vz[X] - L.vz[q], L.m[X] + L.m[q], p, sq, s64, h))
                 atomicOr(&L.flag[X >> 5], 1u << (X & 31));
         }
-        __syncthreads();
+        sync();
         // all-pairs sweep of the sets that are not stars
-        for (int a = threadIdx.x; a < n; a += TPB) {
+        for (int a = tid(); a < n; a += NT) {
             if (!is_main(L, a)) continue;
             const int s = L.segS[a];
             if (!bit_of(L.flag, s)) continue;
@@ -1037,16 +1055,16 @@ struct SmallKernel {
             tau += (unsigned long long)(e - a - 1);
         }
         count(L, ST_TAU, tau);
-        __syncthreads();
+        sync();
         // labels and sizes
-        for (int a = threadIdx.x; a < n; a += TPB) {
+        for (int a = tid(); a < n; a += NT) {
             if (!is_main(L, a)) continue;
             const int s = L.segS[a];
             const int lab = bit_of(L.flag, s) ? lfind(L.par, a) : s;
             L.cid[a] = (int16_t)lab;
             atomicAdd(&L.cnt[lab], 1);
         }
-        __syncthreads();
+        sync();
         scan_cnt(L);
         // destination of every position: components in label order, members
         // in position order
@@ -1054,7 +1072,7 @@ struct SmallKernel {
         unsigned long long comps = 0, splits = 0, alg = 0;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int a = threadIdx.x + e * TPB;
+            const int a = tid() + e * NT;
             dst[e] = -1;
             if (a >= n || !is_main(L, a)) continue;
             const int s = L.segS[a];
@@ -1081,14 +1099,14 @@ struct SmallKernel {
         int16_t re[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int a = threadIdx.x + e * TPB;
+            const int a = tid() + e * NT;
             if (dst[e] < 0) continue;
             rx[e] = L.x[a]; ry[e] = L.y[a]; rz[e] = L.z[a];
             rvx[e] = L.vx[a]; rvy[e] = L.vy[a]; rvz[e] = L.vz[a]; rm[e] = L.m[a];
             ro[e] = L.orig[a];
             re[e] = L.entry[a];
         }
-        __syncthreads();
+        sync();
         bool any_nt = false;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -1104,10 +1122,10 @@ struct SmallKernel {
                 any_nt = true;
             }
         }
-        if (threadIdx.x == 0) L.hasnt[k] = 0;
-        __syncthreads();
+        if (tid() == 0) L.hasnt[k] = 0;
+        sync();
         if (any_nt) L.hasnt[k] = 1;
-        __syncthreads();
+        sync();
     }
 
     // Drift R by h/2, kick every pair of a main set in different components by
@@ -1119,7 +1137,7 @@ struct SmallKernel {
         const double hh = 0.5 * h;
         unsigned long long drifts = 0, kicks = 0;
         bool ok = true;
-        for (int a = threadIdx.x; a < n; a += TPB) {
+        for (int a = tid(); a < n; a += NT) {
             if (!is_main(L, a)) continue;
             int wi = a >> 5;
             uint32_t bits = L.cs[k][wi] & (0xFFFFFFFFu >> (31 - (a & 31)));
@@ -1132,10 +1150,10 @@ struct SmallKernel {
                 drifts++;
             }
         }
-        __syncthreads();
+        sync();
         // Partner order: with EXACT, ascending original index (the order of a
         // sequential i<j sweep over the set); otherwise slot order.
-        for (int a = threadIdx.x; a < n; a += TPB) {
+        for (int a = tid(); a < n; a += NT) {
             if (!is_main(L, a)) continue;
             const int s = L.segS[a], e = L.segE[a];
             bool multi = false;
@@ -1153,8 +1171,8 @@ struct SmallKernel {
                 L.aux[a] = (int16_t)a;
             }
         }
-        __syncthreads();
-        for (int a = threadIdx.x; a < n; a += TPB) {
+        sync();
+        for (int a = tid(); a < n; a += NT) {
             if (!is_main(L, a)) continue;
             const int s = L.segS[a], e = L.segE[a];
             if (L.aux[s] < 0) continue;  // a single component: nothing to kick
@@ -1190,8 +1208,8 @@ struct SmallKernel {
             L.vz[a] += h * az;
         }
         if (!ok) atomicOr(&L.err, EB_NONFINITE);
-        __syncthreads();
-        for (int a = threadIdx.x; a < n; a += TPB) {
+        sync();
+        for (int a = tid(); a < n; a += NT) {
             if (!is_main(L, a)) continue;
             if (!bit_of(L.nt[k], a)) {
                 L.x[a] += hh * L.vx[a];
@@ -1202,34 +1220,34 @@ struct SmallKernel {
         }
         count(L, ST_DRIFT, drifts);
         count(L, ST_KICK, kicks);
-        __syncthreads();
+        sync();
     }
 
     static __device__ void run_item(SoA Wg, SmallLDS<CAP> &L, const Seg g, double H, const DevParams &p,
                                     int32_t *err, uint64_t *stats, uint64_t *fam)
     {
         const int n = g.n;
-        for (int a = threadIdx.x; a < n; a += TPB) {
+        for (int a = tid(); a < n; a += NT) {
             const int u = g.start + a;
             L.x[a] = Wg.x[u]; L.y[a] = Wg.y[u]; L.z[a] = Wg.z[u];
             L.vx[a] = Wg.vx[u]; L.vy[a] = Wg.vy[u]; L.vz[a] = Wg.vz[u]; L.m[a] = Wg.m[u];
             L.orig[a] = Wg.orig[u];
             L.entry[a] = (int16_t)a;
         }
-        if (threadIdx.x < 8) L.ctr[threadIdx.x] = 0;
-        if (threadIdx.x == 0) {
+        if (tid() < 8) L.ctr[tid()] = 0;
+        if (tid() == 0) {
             L.err = 0;
             L.maxd = -1;
             L.phase[0] = 0;
         }
-        __syncthreads();
+        sync();
         int k = 0;
         double h = H;
         uint64_t visits = 0;
         for (;;) {
             if (++visits > ITEM_VISIT_BUDGET) {
-                if (threadIdx.x == 0) L.err |= EB_BUDGET;
-                __syncthreads();
+                if (tid() == 0) L.err |= EB_BUDGET;
+                sync();
                 break;
             }
             int ph = L.phase[k];
@@ -1238,18 +1256,18 @@ struct SmallKernel {
             if (ph == 0) {
                 const int depth = g.depth + k;
                 if (depth > p.max_depth || k >= MAXL - 1) {
-                    if (threadIdx.x == 0) L.err |= EB_DEPTH;
-                    __syncthreads();
+                    if (tid() == 0) L.err |= EB_DEPTH;
+                    sync();
                     break;
                 }
-                if (threadIdx.x == 0) atomicMax(&L.maxd, depth);
+                if (tid() == 0) atomicMax(&L.maxd, depth);
                 enumerate(L, k, n, true);
                 run_binaries(L, h, depth, p);
                 if (L.err) break;
                 split(L, k, n, h, p);
                 if (L.hasnt[k]) {
                     descend = true;
-                    if (threadIdx.x == 0) L.phase[k] = 1;
+                    if (tid() == 0) L.phase[k] = 1;
                 } else {
                     ph = 1;
                     fresh = true;
@@ -1261,65 +1279,67 @@ struct SmallKernel {
                 if (L.err) break;
                 if (L.hasnt[k]) {
                     descend = true;
-                    if (threadIdx.x == 0) L.phase[k] = 2;
+                    if (tid() == 0) L.phase[k] = 2;
                 }
             }
             if (descend) {
-                if (threadIdx.x == 0) L.phase[k + 1] = 0;
-                __syncthreads();
+                if (tid() == 0) L.phase[k + 1] = 0;
+                sync();
                 k++;
                 h = 0.5 * h;
                 continue;
             }
             // level k finished (both halves, or no components)
-            __syncthreads();
+            sync();
             if (k == 0) break;
             k--;
             h = 2.0 * h;
         }
-        __syncthreads();
+        sync();
         if (L.err) {
-            if (threadIdx.x == 0) atomicOr(err, L.err);
+            if (tid() == 0) atomicOr(err, L.err);
         } else {
-            for (int a = threadIdx.x; a < n; a += TPB) {
+            for (int a = tid(); a < n; a += NT) {
                 const int u = g.start + L.entry[a];
                 Wg.x[u] = L.x[a]; Wg.y[u] = L.y[a]; Wg.z[u] = L.z[a];
                 Wg.vx[u] = L.vx[a]; Wg.vy[u] = L.vy[a]; Wg.vz[u] = L.vz[a];
             }
         }
-        if (threadIdx.x < 7 && threadIdx.x != ST_MAXD) stat_add(stats, g.cluster, threadIdx.x, L.ctr[threadIdx.x]);
-        if (threadIdx.x == 0) {
+        if (tid() < 7 && tid() != ST_MAXD) stat_add(stats, g.cluster, tid(), L.ctr[tid()]);
+        if (tid() == 0) {
             fam_add(fam, 0, L.ctr[ST_TAU]);
             fam_add(fam, 1, L.ctr[ST_KICK]);
         }
-        if (threadIdx.x == 0 && L.maxd >= 0) stat_max(stats, g.cluster, L.maxd);
-        __syncthreads();
+        if (tid() == 0 && L.maxd >= 0) stat_max(stats, g.cluster, L.maxd);
+        sync();
     }
 };
 
 struct SmallItems {
     const Seg *bin[4];
-    const int32_t *count;  // counts of bins 0..3 at count[0..3]
-    int32_t cap;
+    const int32_t *count;  // counts of bins 0..3 at count[0..3]; count[-1] = two-particle components
+    int32_t cap;           // capacity of each bin list
+    int32_t cap_pairs;     // capacity of the two-particle list
 };
 
-template <int CAP, int MODE>
-__global__ __launch_bounds__(TPB) void k_small(SoA W, SmallItems items, int32_t *qhead, int32_t *qdone, double H,
-                                                DevParams p, int32_t *err, uint64_t *stats, uint64_t *fam)
+// A team of NT threads (the workgroup, or one wavefront with its own LDS
+// region) takes items of bins [blo, bhi] from a queue, largest sizes first.
+template <int CAP, int MODE, int NT>
+__device__ void run_team(SoA W, SmallLDS<CAP> &L, const SmallItems &items, int blo, int bhi, int32_t *qhead,
+                         double H, const DevParams &p, int32_t *err, uint64_t *stats, uint64_t *fam)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    SmallLDS<CAP> &L = *reinterpret_cast<SmallLDS<CAP> *>(smem_raw);
-    int c[4];
-    for (int b = 0; b < 4; ++b) c[b] = min(items.count[b], items.cap);
+    using K = SmallKernel<CAP, MODE, NT>;
+    const int tid = K::tid();
+    int c[4] = {0, 0, 0, 0};
+    for (int b = blo; b <= bhi; ++b) c[b] = min(items.count[b], items.cap);
     const int total = c[0] + c[1] + c[2] + c[3];
     for (;;) {
-        if (threadIdx.x == 0) L.item = atomicAdd(qhead, 1);
-        __syncthreads();
+        if (tid == 0) L.item = atomicAdd(qhead, 1);
+        K::sync();
         int it = L.item;
-        __syncthreads();
+        K::sync();
         if (it >= total) break;
-        // largest sizes first
-        int b = 3;
+        int b = bhi;
         while (it >= c[b]) {
             it -= c[b];
             b--;
@@ -1327,7 +1347,7 @@ __global__ __launch_bounds__(TPB) void k_small(SoA W, SmallItems items, int32_t 
         const Seg g = items.bin[b][it];
         if (g.n == 1) {
             // a lone particle: split gives R = {it}; drift h/2 twice
-            if (threadIdx.x == 0) {
+            if (tid == 0) {
                 const int u = g.start;
                 const double hh = 0.5 * H;
                 for (int r = 0; r < 2; ++r) {
@@ -1341,15 +1361,42 @@ __global__ __launch_bounds__(TPB) void k_small(SoA W, SmallItems items, int32_t 
             }
             continue;
         }
-        SmallKernel<CAP, MODE>::run_item(W, L, g, H, p, err, stats, fam);
+        K::run_item(W, L, g, H, p, err, stats, fam);
     }
-    // The last block to leave resets the queue for the next launch on it (each
-    // block took its final, out-of-range ticket before counting itself out).
+}
+
+// The components of one level that are evolved on chip, in one launch: the
+// first nbp blocks take the two-particle components one per thread, the next
+// nbb blocks the components of bins 2-3 one per workgroup, the rest the
+// components of bins 0-1 one per wavefront.  q[0], q[1] are the heads of the
+// workgroup and wavefront queues, q[2] counts finished blocks; all three are
+// 0 before a launch and the last block to finish resets them.
+template <int CAP, int MODE>
+__global__ __launch_bounds__(TPB) void k_items(SoA W, const Seg *__restrict__ pairs, SmallItems items, int nbp,
+                                                int nbb, int32_t *q, double H, DevParams p, int32_t *err,
+                                                uint64_t *stats, uint64_t *fam)
+{
+    constexpr bool MIXED = (MODE == 2);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int bid = blockIdx.x;
+    if (bid < nbp) {
+        const int n = min(items.count[-1], items.cap_pairs);
+        run_pairs<MIXED>(W, pairs, n, bid * TPB + threadIdx.x, nbp * TPB, H, p, err, stats, fam);
+    } else if (bid < nbp + nbb) {
+        SmallLDS<CAP> &L = *reinterpret_cast<SmallLDS<CAP> *>(smem_raw);
+        run_team<CAP, MODE, TPB>(W, L, items, 2, 3, &q[0], H, p, err, stats, fam);
+    } else {
+        SmallLDS<SMALL_WAVE_CAP> &L = reinterpret_cast<SmallLDS<SMALL_WAVE_CAP> *>(smem_raw)[threadIdx.x / WAVE];
+        run_team<SMALL_WAVE_CAP, MODE, WAVE>(W, L, items, 0, 1, &q[1], H, p, err, stats, fam);
+    }
+    // Each team took its final, out-of-range ticket before its block counts out.
+    __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
-        if (atomicAdd(qdone, 1) == (int)gridDim.x - 1) {
-            atomicExch(qhead, 0);
-            atomicExch(qdone, 0);
+        if (atomicAdd(&q[2], 1) == (int)gridDim.x - 1) {
+            atomicExch(&q[0], 0);
+            atomicExch(&q[1], 0);
+            atomicExch(&q[2], 0);
         }
     }
 }
@@ -1640,63 +1687,52 @@ hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, c
     return hipGetLastError();
 }
 
-hipError_t launch_pairs(SoA W, const Seg *items, const int32_t *count, int cap, int nitems, double H, DevParams p,
-                        bool mixed, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
-{
-    if (nitems <= 0) return hipSuccess;
-    if (mixed)
-        hipLaunchKernelGGL(k_pairs<true>, dim3(nblocks(nitems, 4096)), dim3(TPB), 0, st, W, items, count, cap, H, p,
-                           err, stats, fam);
-    else
-        hipLaunchKernelGGL(k_pairs<false>, dim3(nblocks(nitems, 4096)), dim3(TPB), 0, st, W, items, count, cap, H, p,
-                           err, stats, fam);
-    return hipGetLastError();
-}
-
 template <int CAP, int MODE>
-static hipError_t launch_small_cap(SoA W, const SmallArgs &s, double H, DevParams p, int32_t *err, uint64_t *stats,
-                                   uint64_t *fam, int nblk, hipStream_t st)
+static hipError_t launch_items_cap(SoA W, const SmallArgs &s, int nbp, int nbb, int nbw, double H, DevParams p,
+                                   int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
     static bool configured = false;
-    const size_t lds = sizeof(SmallLDS<CAP>);
+    const size_t lds = std::max(sizeof(SmallLDS<CAP>), sizeof(SmallLDS<SMALL_WAVE_CAP>) * (TPB / WAVE));
     if (!configured) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_small<CAP, MODE>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_items<CAP, MODE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         configured = true;
     }
     SmallItems it{};
     for (int b = 0; b < 4; ++b) it.bin[b] = s.bin[b];
-    it.count = s.count;
+    it.count = s.count + 1;
     it.cap = s.cap;
-    hipLaunchKernelGGL((k_small<CAP, MODE>), dim3(nblk), dim3(TPB), lds, st, W, it, s.qhead, s.qdone, H, p, err, stats,
-                       fam);
+    it.cap_pairs = s.cap_pairs;
+    hipLaunchKernelGGL((k_items<CAP, MODE>), dim3(nbp + nbb + nbw), dim3(TPB), lds, st, W, s.pairs, it, nbp, nbb,
+                       s.queue, H, p, err, stats, fam);
     return hipGetLastError();
 }
 
-size_t small_lds_bytes(int cap)
+size_t items_lds_bytes(int cap)
 {
-    if (cap <= 256) return sizeof(SmallLDS<256>);
-    if (cap <= 512) return sizeof(SmallLDS<512>);
-    return sizeof(SmallLDS<1024>);
+    const size_t w = sizeof(SmallLDS<SMALL_WAVE_CAP>) * (TPB / WAVE);
+    if (cap <= 256) return std::max(sizeof(SmallLDS<256>), w);
+    if (cap <= 512) return std::max(sizeof(SmallLDS<512>), w);
+    return std::max(sizeof(SmallLDS<1024>), w);
 }
 
-hipError_t launch_small(SoA W, const SmallArgs &s, int cap, int mode, double H, DevParams p, int32_t *err,
-                        uint64_t *stats, uint64_t *fam, int nblk, hipStream_t st)
+hipError_t launch_items(SoA W, const SmallArgs &s, int cap, int mode, int nbp, int nbb, int nbw, double H,
+                        DevParams p, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
-    if (nblk <= 0) return hipSuccess;
-#define CC_SMALL_CAPS(M)                                                                  \
-    if (cap <= 256) return launch_small_cap<256, M>(W, s, H, p, err, stats, fam, nblk, st); \
-    if (cap <= 512) return launch_small_cap<512, M>(W, s, H, p, err, stats, fam, nblk, st); \
-    return launch_small_cap<1024, M>(W, s, H, p, err, stats, fam, nblk, st);
+    if (nbp + nbb + nbw <= 0) return hipSuccess;
+#define CC_ITEMS_CAPS(M)                                                                               \
+    if (cap <= 256) return launch_items_cap<256, M>(W, s, nbp, nbb, nbw, H, p, err, stats, fam, st); \
+    if (cap <= 512) return launch_items_cap<512, M>(W, s, nbp, nbb, nbw, H, p, err, stats, fam, st); \
+    return launch_items_cap<1024, M>(W, s, nbp, nbb, nbw, H, p, err, stats, fam, st);
     if (mode == 1) {
-        CC_SMALL_CAPS(1)
+        CC_ITEMS_CAPS(1)
     }
     if (mode == 2) {
-        CC_SMALL_CAPS(2)
+        CC_ITEMS_CAPS(2)
     }
-    CC_SMALL_CAPS(0)
-#undef CC_SMALL_CAPS
+    CC_ITEMS_CAPS(0)
+#undef CC_ITEMS_CAPS
 }
 
 int diag_blocks(int n) { return nblocks(n, 1 << 30); }

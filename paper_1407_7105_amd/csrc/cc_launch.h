@@ -40,11 +40,11 @@ struct ListArgs {
 };
 
 struct SmallArgs {
-    const Seg *bin[4];
-    const int32_t *count;  // 4 bin counts
-    int32_t cap;
-    int32_t *qhead;  // work-queue head, 0 before a launch; the launch's last block resets it
-    int32_t *qdone;  // blocks finished, likewise reset
+    const Seg *pairs;      // two-particle components
+    const Seg *bin[4];     // other on-chip components by size bin
+    const int32_t *count;  // [0] pairs, [1..4] bins
+    int32_t cap, cap_pairs;
+    int32_t *queue;        // 3 ints, 0 before a launch: workgroup and wavefront queue heads, blocks finished
 };
 
 hipError_t launch_validate(const double *x, const double *y, const double *z, const double *vx, const double *vy,
@@ -84,12 +84,13 @@ hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, doub
                            double *az, int32_t *err, hipStream_t st);
 hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, const double *az, double h,
                              hipStream_t st);
-hipError_t launch_pairs(SoA W, const Seg *items, const int32_t *count, int cap, int nitems, double H, DevParams p,
-                        bool mixed, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
-size_t small_lds_bytes(int cap);
-// mode: 0 = FP64 slot order, 1 = FP64 ascending index order, 2 = mixed precision
-hipError_t launch_small(SoA W, const SmallArgs &s, int cap, int mode, double H, DevParams p, int32_t *err,
-                        uint64_t *stats, uint64_t *fam, int nblk, hipStream_t st);
+// One launch for a level's on-chip components: nbp blocks of two-particle
+// components (one per thread), nbb blocks of bins 2-3 (one per workgroup,
+// cap = largest size), nbw blocks of bins 0-1 (one per wavefront).
+// mode: 0 = FP64 slot order, 1 = FP64 ascending index order, 2 = mixed.
+size_t items_lds_bytes(int cap);
+hipError_t launch_items(SoA W, const SmallArgs &s, int cap, int mode, int nbp, int nbb, int nbw, double H,
+                        DevParams p, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
 int diag_blocks(int n);
 hipError_t launch_diag(SoA S, int n, double eps2, double G, double *part, double *out, hipStream_t st);
 
