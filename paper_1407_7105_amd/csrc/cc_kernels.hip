@@ -251,7 +251,11 @@ __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg
 // particle whose local root has a different global root into the global
 // structure: at most one global union per particle per tile.
 constexpr int ST = 64;  // sweep tile edge (one wavefront)
-constexpr int SWEEP_SPLIT_TILES = 2048;  // launches up to this many tiles use one block per tile
+// Launches of few tiles split each tile's partners over JS = 4 wavefronts so
+// that the partner loops are short (up to SWEEP_SPLIT4_TILES tiles; a split
+// in two for mid-size launches measured slower than none).
+constexpr int SWEEP_SPLIT4_TILES = 2048;
+constexpr int SWEEP_SPLIT2_TILES = 2048;
 
 // One ST x ST tile of a set's pair triangle per JS wavefronts: wavefront
 // jpart of the tile takes the tile's i particles against its ST/JS partners
@@ -333,6 +337,8 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
         // literal formula), with a loop that is uniform across the
         // wavefront; then resolve the undecided pairs and link the edges.
         uint64_t emask = 0, umask = 0;
+        // two partners per trip: independent chains hide FP64 latency
+#pragma unroll 2
         for (int jj = 0; jj < jnw; ++jj) {
             const int d = edge_screen<MIXED>(xi - jx[w][jj], yi - jy[w][jj], zi - jz[w][jj], vxi - jvx[w][jj],
                                              vyi - jvy[w][jj], vzi - jvz[w][jj], mi + jm[w][jj], p, q, s64);
@@ -1552,25 +1558,22 @@ hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, i
                         bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
     if (a.ntiles == 0) return hipSuccess;
-    // launches of few tiles give each tile a whole block (4 wavefronts of
-    // 16 partners each) so the partner loops are short
-    const bool split = a.ntiles <= SWEEP_SPLIT_TILES;
-    const int nb = split ? a.ntiles : (a.ntiles + TPB / ST - 1) / (TPB / ST);
+    const int js = a.ntiles <= SWEEP_SPLIT4_TILES ? 4 : a.ntiles <= SWEEP_SPLIT2_TILES ? 2 : 1;
+    const int tpb = (TPB / ST) / js;  // tiles per block
+    const int nb = (a.ntiles + tpb - 1) / tpb;
+#define CC_SWEEP(M, J)                                                                                          \
+    hipLaunchKernelGGL((k_sweep<M, J>), dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar, a.epoch, \
+                       parent, p, h, stats, fam)
     if (mixed) {
-        if (split)
-            hipLaunchKernelGGL((k_sweep<true, 4>), dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar,
-                               a.epoch, parent, p, h, stats, fam);
-        else
-            hipLaunchKernelGGL((k_sweep<true, 1>), dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar,
-                               a.epoch, parent, p, h, stats, fam);
+        if (js == 4) CC_SWEEP(true, 4);
+        else if (js == 2) CC_SWEEP(true, 2);
+        else CC_SWEEP(true, 1);
     } else {
-        if (split)
-            hipLaunchKernelGGL((k_sweep<false, 4>), dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg,
-                               notstar, a.epoch, parent, p, h, stats, fam);
-        else
-            hipLaunchKernelGGL((k_sweep<false, 1>), dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg,
-                               notstar, a.epoch, parent, p, h, stats, fam);
+        if (js == 4) CC_SWEEP(false, 4);
+        else if (js == 2) CC_SWEEP(false, 2);
+        else CC_SWEEP(false, 1);
     }
+#undef CC_SWEEP
     return hipGetLastError();
 }
 
