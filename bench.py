@@ -7,6 +7,11 @@ drift/kick/drift), started each time from the same initial conditions, which
 are already resident in HBM.  `value` is algorithmic pair interactions per
 second: the pair time steps the splits need (n-1 for a fully connected set,
 n(n-1)/2 otherwise) plus the pairs kicked, divided by the wall time per step.
+
+The line also carries an eta scan (`eta_scan`, skipped with --no-eta-scan):
+the same workload integrated for four global steps with FP64 and with mixed
+precision at several eta, its energy error |dE/E| and wall seconds per N-body
+time unit, and for each precision the largest eta that keeps |dE/E| <= 1e-6.
 """
 from __future__ import annotations
 
@@ -21,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
+METRIC = "pair interactions/s; wall-s per N-body time, FP64 vs mixed @ same |dE/E|"
 FLOP_TAU = 48      # FP64 operations of one pair time step, eq. 19 (div and sqrt counted as 1)
 FLOP_KICK = 26     # FP64 operations of one symmetric pair kick, eqs. 8-9
 PEAK_FP64_VECTOR = 78.6e12   # MI355X: 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
@@ -47,6 +53,43 @@ def cpu_baseline(p, dt, eta):
                       f"evaluations) and 4 all-pair kicks ({pairs} pairs); {t1 - t0:.1f} s on one host thread"}
 
 
+def eta_scan(p, wl, dev, small_max, etas=(0.01, 0.03, 0.1, 0.3), steps=4, bound=1e-6):
+    """FP64 against mixed precision at equal energy error: each precision is
+    run at every eta for `steps` global steps from the same initial conditions;
+    |dE/E| comes from the library's compensated diagnostics (eqs. 1-3)."""
+    import torch
+
+    from paper_1407_7105_amd import CC_FP64, CC_MIXED, Context, State
+    dt = wl["dt"]
+    rows = []
+    for name, prec in (("fp64", CC_FP64), ("mixed", CC_MIXED)):
+        for eta in etas:
+            ctx = Context(device=0, eta=eta, eps2=wl["eps2"], precision=prec, small_max=small_max)
+            s = State.from_numpy(p, device=dev)
+            e0 = ctx.diagnostics(s)["energy"]
+            ctx.evolve(s, dt, dt)  # warm-up of this context's buffers, then the timed run from the start
+            s = State.from_numpy(p, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.evolve(s, dt, steps * dt)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            e1 = ctx.diagnostics(s)["energy"]
+            rows.append({"precision": name, "eta": eta, "dE_over_E": abs((e1 - e0) / e0),
+                         "wall_s_per_nbody_time": wall / (steps * dt)})
+            print(f"# eta scan {name} eta={eta}: |dE/E|={rows[-1]['dE_over_E']:.3e} "
+                  f"{rows[-1]['wall_s_per_nbody_time']:.3f} s per N-body time", file=sys.stderr, flush=True)
+    chosen = {}
+    for name in ("fp64", "mixed"):
+        ok = [r for r in rows if r["precision"] == name and r["dE_over_E"] <= bound]
+        chosen[name] = max(ok, key=lambda r: r["eta"]) if ok else None
+    ratio = None
+    if chosen["fp64"] and chosen["mixed"]:
+        ratio = chosen["fp64"]["wall_s_per_nbody_time"] / chosen["mixed"]["wall_s_per_nbody_time"]
+    return {"t": steps * dt, "bound": bound, "rows": rows, "chosen": chosen,
+            "mixed_speedup_at_equal_dE": ratio}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -56,6 +99,7 @@ def main():
     ap.add_argument("--small-max", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--no-eta-scan", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -116,8 +160,10 @@ def main():
                 "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64_VECTOR / 1e12), "traffic": None,
                 "avg_launch_ms": d["ms"] / d["launches"], "launches_per_step": d["launches"] / args.steps}
 
+    scan = None if args.no_eta_scan else eta_scan(p, wl, dev, args.small_max)
+
     out = {
-        "metric": "pair interactions/s", "value": value, "unit": "pairs/s", "n_gpus": 1,
+        "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == CC_FP64 else "f32+f64",
         "data": "synthetic",
@@ -128,6 +174,7 @@ def main():
         "roofline": roof,
         "kernel_ms_per_step": None if fam is None else
         {k: round(v["ms"] / args.steps, 4) for k, v in fam.items() if v["launches"]},
+        "eta_scan": scan,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, dt, eta)

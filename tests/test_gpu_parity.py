@@ -415,3 +415,61 @@ def test_mixed_step_conservation_and_accuracy(cfg, n):
     pscale = np.sum(s.m * np.linalg.norm(s.vel(), axis=1))
     assert np.all(np.abs(d1["P"] - d0["P"]) < 1e-6 * pscale)
     assert abs(d1["energy"] / d0["energy"] - 1) < 1e-5
+
+
+# ------------------------------------------------------------------ full sizes
+
+def _sampled_component_check(s, lab, h, p, nsample, seed):
+    """Every edge (tau < h, from the oracle, one particle against all others)
+    at sampled particles joins particles of one component, and labels are
+    canonical (the smallest index of the component)."""
+    n = s.n
+    assert np.all(lab <= np.arange(n)) and np.all(lab[lab] == lab)
+    rng = np.random.default_rng(seed)
+    for i in rng.choice(n, nsample, replace=False):
+        pj = np.arange(n, dtype=np.int32)
+        pi = np.full(n, i, dtype=np.int32)
+        tau = oracle.pair_timesteps(s, pi, pj, p)
+        tau[i] = np.inf
+        nb = np.flatnonzero(tau < h)
+        assert np.all(lab[nb] == lab[i]), f"particle {i}: neighbours in other components"
+
+
+@pytest.mark.parametrize("precision", [CC_FP64, CC_MIXED])
+@pytest.mark.parametrize("cfg", [3, 5])
+def test_split_full_size_sampled(cfg, precision):
+    """Top-level split of the 65 536-body fractal and the 262 144-body Plummer
+    workloads at dt = 1/64, in the sweep configuration the integrator uses."""
+    s = synth.workload(cfg)
+    p = oracle.Params(eta=0.01)
+    ctx = ctx_for(p, precision=precision)
+    lab, nt = ctx.split_labels(State.from_numpy(s), 1 / 64)
+    lab = lab.cpu().numpy()
+    _sampled_component_check(s, lab, 1 / 64, p, nsample=48, seed=cfg)
+    sizes = np.bincount(lab, minlength=s.n)
+    assert nt == int(np.count_nonzero(sizes >= 2))
+
+
+def test_ensemble_full_size_sampled_clusters_bitwise():
+    """The 1024-cluster ensemble (N per cluster in [16, 512], 20% binaries,
+    hard binaries reaching 20+ levels) integrated for four global steps in one
+    batch; sampled clusters, run one by one through the oracle (seconds each),
+    agree bit for bit, statistics included."""
+    s = synth.workload(4)
+    off = s.offsets
+    sizes = np.diff(off)
+    p = oracle.Params(eta=0.01)
+    g = State.from_numpy(s)
+    t_end = 4 / 64
+    sts = ctx_for(p).evolve_batch(g, off, 1 / 64, t_end)
+    got = g.to_numpy()
+    rng = np.random.default_rng(4)
+    picks = {int(np.argmax(sizes)), int(np.argmin(sizes))} | set(int(c) for c in rng.choice(len(sizes), 3, replace=False))
+    for c in sorted(picks):
+        a, b = off[c], off[c + 1]
+        one = Particles(*(getattr(s, f)[a:b].copy() for f in ("x", "y", "z", "vx", "vy", "vz", "m")))
+        _, ost = oracle.evolve(one, 1 / 64, t_end, p)
+        for f in State.FIELDS:
+            assert np.array_equal(got[f][a:b], getattr(one, f)), (c, f)
+        for k in STAT_KEYS:
+            assert sts[c][k] == ost[k], (c, k, sts[c][k], ost[k])
