@@ -56,6 +56,13 @@ typedef enum {
                                sequential FP64 evaluation of the same formulas */
 } cc_kick_order;
 
+typedef enum {
+    CC_SCREEN_FP64 = 0,     /* edge test screened by a division-free FP64 form with a
+                               certified error bound (the default) */
+    CC_SCREEN_FP32 = 1      /* FP32 screen on FP32-rounded differences first, then the
+                               FP64 screen; on gfx950 without packed FP32 this is slower */
+} cc_screen;
+
 typedef struct cc_ctx cc_ctx;
 
 typedef struct {
@@ -73,6 +80,9 @@ typedef struct {
     int32_t small_max;      /* largest component integrated on chip by one
                                workgroup (3..1024; 0 = library default) */
     int32_t kick_order;     /* cc_kick_order */
+    int32_t screen;         /* cc_screen for the grid-wide star test and sweep; either
+                               screen leaves undecided pairs to the literal FP64 formula,
+                               so partitions do not depend on it */
 } cc_params;
 
 typedef struct {

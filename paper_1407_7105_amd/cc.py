@@ -18,6 +18,7 @@ _LIB_PATH = os.path.join(_HERE, "libcc_mi355x.so")
 CC_OK, CC_ERR_ARG, CC_ERR_NONFINITE, CC_ERR_DEPTH, CC_ERR_DEVICE, CC_ERR_OOM = 0, -1, -2, -3, -4, -5
 CC_FP64, CC_MIXED = 0, 1
 CC_ORDER_FAST, CC_ORDER_EXACT = 0, 1
+CC_SCREEN_FP64, CC_SCREEN_FP32 = 0, 1
 
 # entry points declared in include/cc.h
 SYMBOLS = ("cc_create", "cc_destroy", "cc_set_params", "cc_last_error", "cc_pair_timesteps", "cc_split_labels",
@@ -31,7 +32,8 @@ class _State(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("eta", C.c_double), ("eps2", C.c_double), ("G", C.c_double), ("max_depth", C.c_int32),
-                ("precision", C.c_int32), ("small_max", C.c_int32), ("kick_order", C.c_int32)]
+                ("precision", C.c_int32), ("small_max", C.c_int32), ("kick_order", C.c_int32),
+                ("screen", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -145,9 +147,9 @@ class Context:
 
     def __init__(self, device: int = 0, eta: float = 0.01, eps2: float = 0.0, G: float = 1.0,
                  max_depth: int = 48, precision: int = CC_FP64, small_max: int = 0,
-                 kick_order: int = CC_ORDER_FAST):
+                 kick_order: int = CC_ORDER_FAST, screen: int = CC_SCREEN_FP64):
         self._L = load_library()
-        self._p = _Params(eta, eps2, G, max_depth, precision, small_max, kick_order)
+        self._p = _Params(eta, eps2, G, max_depth, precision, small_max, kick_order, screen)
         h = C.c_void_p()
         rc = self._L.cc_create(C.byref(h), device, C.byref(self._p))
         if rc != CC_OK:

@@ -164,6 +164,9 @@ bool mixed(const cc_ctx *c) { return c->params.precision == CC_MIXED; }
 // The mixed path sums kicks over parallel tiles; EXACT order applies to FP64.
 bool exact_order(const cc_ctx *c) { return !mixed(c) && c->params.kick_order == CC_ORDER_EXACT; }
 
+// FP32 screen in front of the FP64 one in the grid-wide star test and sweep
+bool screen32(const cc_ctx *c) { return c->params.screen == CC_SCREEN_FP32; }
+
 int check_params(cc_ctx *c, const cc_params *p)
 {
     if (!p) return fail(c, CC_ERR_ARG, "params is NULL");
@@ -176,6 +179,7 @@ int check_params(cc_ctx *c, const cc_params *p)
         return fail(c, CC_ERR_ARG, "small_max must be 0 or in [3, 1024]");
     if (p->kick_order != CC_ORDER_FAST && p->kick_order != CC_ORDER_EXACT)
         return fail(c, CC_ERR_ARG, "unknown kick_order");
+    if (p->screen != CC_SCREEN_FP64 && p->screen != CC_SCREEN_FP32) return fail(c, CC_ERR_ARG, "unknown screen");
     return CC_OK;
 }
 
@@ -527,11 +531,12 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     }
     {
         Span s(c, F_STAR);
-        HIPCHK(launch_star(W, a, lv.notstar, c->parent, c->cnt, p, h, mixed(c), c->stats, fam_ptr(c, F_STAR), c->st));
+        HIPCHK(launch_star(W, a, lv.notstar, c->parent, c->cnt, p, h, screen32(c), c->stats, fam_ptr(c, F_STAR),
+                           c->st));
     }
     {
         Span s(c, F_SWEEP);
-        HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, mixed(c), c->stats, fam_ptr(c, F_SWEEP), c->st));
+        HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, screen32(c), c->stats, fam_ptr(c, F_SWEEP), c->st));
     }
     {
         Span s(c, F_LABEL);
@@ -928,8 +933,8 @@ int cc_split_labels(cc_ctx *c, const cc_state *s, int64_t n, double h, int32_t *
     HIPCHK(hipMemsetAsync(c->stats, 0, ST_N * sizeof(uint64_t), c->st));
     const DevParams p = dev_params(c);
     SoA S = user_soa(s);
-    HIPCHK(launch_star(S, a, lv.notstar, c->parent, c->cnt, p, h, mixed(c), c->stats, nullptr, c->st));
-    HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, mixed(c), c->stats, nullptr, c->st));
+    HIPCHK(launch_star(S, a, lv.notstar, c->parent, c->cnt, p, h, screen32(c), c->stats, nullptr, c->st));
+    HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, screen32(c), c->stats, nullptr, c->st));
     HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, c->cnt, nullptr, nullptr, nullptr, c->stats, c->st));
     if (n_nontrivial_out) {
         // roots carry their component size in cnt (zeroed for every slot by the star kernel)

@@ -55,10 +55,12 @@ hipError_t launch_drift_mask(SoA S, int64_t n, const uint8_t *mask, double h, hi
 hipError_t launch_iota(int32_t *a, int64_t n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t st);
 
+// screen32: FP32 screen in front of the FP64 one (the template flag MIXED of
+// the kernels' edge test)
 hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, int32_t *cnt, DevParams p,
-                       double h, bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st);
+                       double h, bool screen32, uint64_t *stats, uint64_t *fam, hipStream_t st);
 hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, DevParams p, double h,
-                        bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st);
+                        bool screen32, uint64_t *stats, uint64_t *fam, hipStream_t st);
 // labels and component sizes; with keys/vals the sort keys of the active
 // particles, with count the work-list counters cleared
 hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,

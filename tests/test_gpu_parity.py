@@ -20,7 +20,8 @@ pytestmark = pytest.mark.gpu
 if not torch.cuda.is_available():  # pragma: no cover
     pytest.skip("no GPU", allow_module_level=True)
 
-from paper_1407_7105_amd import CC_FP64, CC_MIXED, CC_ORDER_EXACT, CC_ORDER_FAST, CCError, Context, State  # noqa: E402
+from paper_1407_7105_amd import (CC_FP64, CC_MIXED, CC_ORDER_EXACT, CC_ORDER_FAST, CC_SCREEN_FP32,  # noqa: E402
+                                 CCError, Context, State)
 
 
 def ctx_for(p: oracle.Params, **kw):
@@ -69,7 +70,9 @@ def test_pair_timesteps_wide_dynamic_range():
 # ------------------------------------------------------------------ split
 
 def check_split(s, h, p, ctx=None, precision=CC_FP64):
-    ctx = ctx or ctx_for(p, precision=precision)
+    # mixed precision is checked with the FP32 screen in front of the FP64 one
+    screen = CC_SCREEN_FP32 if precision == CC_MIXED else 0
+    ctx = ctx or ctx_for(p, precision=precision, screen=screen)
     lab, nt = ctx.split_labels(State.from_numpy(s), h)
     want, want_nt, _ = oracle.split_labels(s, h, p)
     assert np.array_equal(lab.cpu().numpy(), want)
@@ -208,6 +211,17 @@ def test_evolve_plummer256_one_step_bitwise(small_max):
     for k in STAT_KEYS:
         assert st[k] == ost[k], (k, st[k], ost[k])
     assert st["tau_pairs"] > 0
+
+
+def test_evolve_with_fp32_screen_bitwise():
+    """The FP32 screen only decides pairs it can certify, so the grid path with
+    it stays bit-identical to the oracle."""
+    s = synth.plummer(1500, 91, masses="salpeter")
+    p = oracle.Params(eta=0.01)
+    got, ref, st, ost = run_both(s, 1 / 64, 1 / 64, p, small_max=64, screen=CC_SCREEN_FP32)
+    assert_state_equal(got, ref, "fp32 screen")
+    for k in STAT_KEYS:
+        assert st[k] == ost[k], (k, st[k], ost[k])
 
 
 def test_evolve_plummer256_to_t1_bitwise():
@@ -442,7 +456,7 @@ def test_split_full_size_sampled(cfg, precision):
     workloads at dt = 1/64, in the sweep configuration the integrator uses."""
     s = synth.workload(cfg)
     p = oracle.Params(eta=0.01)
-    ctx = ctx_for(p, precision=precision)
+    ctx = ctx_for(p, precision=precision, screen=CC_SCREEN_FP32 if precision == CC_MIXED else 0)
     lab, nt = ctx.split_labels(State.from_numpy(s), 1 / 64)
     lab = lab.cpu().numpy()
     _sampled_component_check(s, lab, 1 / 64, p, nsample=48, seed=cfg)
