@@ -100,6 +100,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-eta-scan", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -124,6 +125,13 @@ def main():
         for f in State.FIELDS:
             getattr(s, f).copy_(getattr(ic, f))
         return ctx.evolve(s, dt, dt)
+
+    tune = None
+    if not args.no_autotune:
+        # launch shapes (on-chip size limit, sweep tiles per workgroup) from
+        # the library's autotuner, on this workload, before anything is timed
+        tune = ctx.autotune(ic, dt)
+        print(f"# autotune: {tune}", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         t = time.perf_counter()
@@ -168,7 +176,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == CC_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "plummer16k_salpeter", "n": p.n, "imf": "salpeter 0.1-100",
-                   "eta": eta, "eps": 0.0, "dt": dt, "step": "one CC global step"},
+                   "eta": eta, "eps": 0.0, "dt": dt, "step": "one CC global step",
+                   "launch_shapes": tune},
         "wall_s_per_nbody_time": (ms / 1e3) / dt,
         "stats_per_step": stats,
         "roofline": roof,

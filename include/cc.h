@@ -168,6 +168,23 @@ int cc_evolve_batch(cc_ctx *ctx, cc_state *s, const int64_t *offsets, int32_t nc
  * mass.  Syncs. */
 int cc_diagnostics(cc_ctx *ctx, const cc_state *s, int64_t n, double *out, void *stream);
 
+/* Autotuner for the launch shapes of the batched recursion (persistent
+ * on-chip kernel and sweep tiles).  Times one global step of the given state
+ * (device SoA as for cc_evolve; only read: every trial runs on a copy) for
+ * each candidate of the largest component run on chip (small_max in
+ * {64, 128, 256, 512}) and of the sweep launches that give each tile a whole
+ * workgroup (up to {0, 512, 2048, 8192} tiles), keeps the fastest in the
+ * context (params.small_max is overwritten) and reports it in *out (may be
+ * NULL).  Partitions and results in the EXACT kick order do not depend on the
+ * choice.  Allocates a copy of the state; syncs. */
+typedef struct {
+    int32_t small_max;          /* chosen on-chip size limit */
+    int32_t sweep_split_tiles;  /* chosen: sweep launches up to this many tiles use one workgroup per tile */
+    double ms_per_step;         /* best time of one global step with the choice */
+    int32_t trials;             /* configurations timed */
+} cc_tune;
+int cc_autotune(cc_ctx *ctx, const cc_state *s, int64_t n, double dt, cc_tune *out, void *stream);
+
 /* Per-kernel timing for roofline reporting.  While enabled, every launch made
  * by cc_evolve / cc_evolve_batch is bracketed by HIP events on its stream and
  * the pair time steps and kicked pairs it processed are counted per kernel

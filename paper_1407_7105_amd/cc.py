@@ -22,8 +22,8 @@ CC_SCREEN_FP64, CC_SCREEN_FP32 = 0, 1
 
 # entry points declared in include/cc.h
 SYMBOLS = ("cc_create", "cc_destroy", "cc_set_params", "cc_last_error", "cc_pair_timesteps", "cc_split_labels",
-           "cc_kick", "cc_drift", "cc_evolve", "cc_evolve_batch", "cc_diagnostics", "cc_timing_enable",
-           "cc_timing_report")
+           "cc_kick", "cc_drift", "cc_evolve", "cc_evolve_batch", "cc_diagnostics", "cc_autotune",
+           "cc_timing_enable", "cc_timing_report")
 
 
 class _State(C.Structure):
@@ -40,6 +40,11 @@ class _Stats(C.Structure):
     _fields_ = [("tau_pairs", C.c_uint64), ("tau_pairs_alg", C.c_uint64), ("kick_pairs", C.c_uint64),
                 ("drifts", C.c_uint64), ("components", C.c_uint64), ("splits", C.c_uint64),
                 ("max_depth_seen", C.c_int64), ("t_reached", C.c_double)]
+
+
+class _Tune(C.Structure):
+    _fields_ = [("small_max", C.c_int32), ("sweep_split_tiles", C.c_int32), ("ms_per_step", C.c_double),
+                ("trials", C.c_int32)]
 
 
 class _KTime(C.Structure):
@@ -76,6 +81,7 @@ def load_library():
     L.cc_evolve.argtypes = [vp, C.POINTER(_State), i64, d, d, C.POINTER(_Stats), vp]
     L.cc_evolve_batch.argtypes = [vp, C.POINTER(_State), C.POINTER(i64), i32, d, d, C.POINTER(_Stats), vp]
     L.cc_diagnostics.argtypes = [vp, C.POINTER(_State), i64, C.POINTER(d), vp]
+    L.cc_autotune.argtypes = [vp, C.POINTER(_State), i64, d, C.POINTER(_Tune), vp]
     L.cc_timing_enable.argtypes = [vp, i32]
     L.cc_timing_report.argtypes = [vp, C.POINTER(_KTime), i32]
     for f in SYMBOLS:
@@ -228,6 +234,15 @@ class Context:
         self._check(self._L.cc_diagnostics(self._h, C.byref(s._c()), s.n, out, _stream()))
         o = np.array(out[:])
         return dict(ekin=o[0], epot=o[1], energy=o[0] + o[1], P=o[2:5], L=o[5:8], com=o[8:11], mass=o[11])
+
+    def autotune(self, s: State, dt: float) -> dict:
+        """Time one global step of s (read only) per launch-shape candidate and
+        keep the fastest in this context; returns the choice."""
+        t = _Tune()
+        self._check(self._L.cc_autotune(self._h, C.byref(s._c()), s.n, dt, C.byref(t), _stream()))
+        self._p.small_max = t.small_max
+        return dict(small_max=t.small_max, sweep_split_tiles=t.sweep_split_tiles, ms_per_step=t.ms_per_step,
+                    trials=t.trials)
 
     def timing(self, enable: bool):
         self._check(self._L.cc_timing_enable(self._h, 1 if enable else 0))

@@ -35,6 +35,7 @@ constexpr int TPB = 256;
 constexpr int DEFAULT_SMALL_MAX = 256;
 constexpr int kLevels = 64;  // grid recursion levels a context can hold (max_depth <= 60)
 constexpr int SWEEP_TILE = 64;  // edge of the all-pairs sweep tiles
+constexpr int32_t DEFAULT_SWEEP_SPLIT = 2048;
 
 // kernel families for timing
 enum Fam { F_STAR, F_SWEEP, F_LABEL, F_SORT, F_PERMUTE, F_DRIFT, F_KICK, F_PAIRS, F_SMALL, F_VALIDATE, F_OTHER, F_N };
@@ -104,6 +105,7 @@ struct cc_ctx {
     int32_t *h_err = nullptr;
     int32_t *qhead = nullptr;    // per level: head and blocks finished of the workgroup and the wavefront queues
     int32_t epoch = 0;           // visit counter for the non-star flags
+    int32_t sweep_split = DEFAULT_SWEEP_SPLIT;  // sweep launches up to this many tiles: one block per tile
     double *kick_acc = nullptr;  // 3*cap for cc_kick
     double *kick_part = nullptr; // partial accelerations of the tiled kick
     size_t kick_part_cap = 0;    // in kick blocks
@@ -536,7 +538,8 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     }
     {
         Span s(c, F_SWEEP);
-        HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, screen32(c), c->stats, fam_ptr(c, F_SWEEP), c->st));
+        HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, c->stats,
+                            fam_ptr(c, F_SWEEP), c->st));
     }
     {
         Span s(c, F_LABEL);
@@ -934,7 +937,7 @@ int cc_split_labels(cc_ctx *c, const cc_state *s, int64_t n, double h, int32_t *
     const DevParams p = dev_params(c);
     SoA S = user_soa(s);
     HIPCHK(launch_star(S, a, lv.notstar, c->parent, c->cnt, p, h, screen32(c), c->stats, nullptr, c->st));
-    HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, screen32(c), c->stats, nullptr, c->st));
+    HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, c->stats, nullptr, c->st));
     HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, c->cnt, nullptr, nullptr, nullptr, c->stats, c->st));
     if (n_nontrivial_out) {
         // roots carry their component size in cnt (zeroed for every slot by the star kernel)
@@ -985,6 +988,85 @@ int cc_evolve(cc_ctx *c, cc_state *s, int64_t n, double dt, double t_end, cc_sta
     if (!c) return CC_ERR_ARG;
     const int64_t off[2] = {0, n};
     return evolve_common(c, s, n, off, 1, dt, t_end, out, stream);
+}
+
+int cc_autotune(cc_ctx *c, const cc_state *s, int64_t n, double dt, cc_tune *out, void *stream)
+{
+    if (!c) return CC_ERR_ARG;
+    c->err.clear();
+    RC(check_state_ptrs(c, s));
+    if (n < 1) return fail(c, CC_ERR_ARG, "n must be >= 1");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(c, CC_ERR_ARG, "dt must be finite and > 0");
+    HIPCHK(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)stream;
+    // trials run on a copy; the caller's state is only read
+    double *copy[7] = {};
+    const size_t bytes = (size_t)n * sizeof(double);
+    const double *src[7] = {s->x, s->y, s->z, s->vx, s->vy, s->vz, s->m};
+    int rc = CC_OK;
+    for (int a = 0; a < 7 && rc == CC_OK; ++a)
+        if (hipMalloc((void **)&copy[a], bytes) != hipSuccess) rc = fail(c, CC_ERR_OOM, "autotune copy of the state");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == CC_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
+        rc = fail(c, CC_ERR_DEVICE, "autotune events");
+    const cc_params keep = c->params;
+    const int32_t keep_split = c->sweep_split;
+    cc_tune best{keep.small_max, keep_split, 1e300, 0};
+    const int32_t sm_cand[] = {64, 128, 256, 512};
+    const int32_t split_cand[] = {0, 512, 2048, 8192};
+    for (int32_t sm : sm_cand) {
+        if (rc != CC_OK) break;
+        cc_params q = keep;
+        q.small_max = sm;
+        if ((rc = cc_set_params(c, &q)) != CC_OK) break;
+        for (int32_t sp : split_cand) {
+            c->sweep_split = sp;
+            float best_ms = 1e30f;
+            // one untimed step (buffers sized for this setting), then two timed
+            for (int trial = 0; trial < 3 && rc == CC_OK; ++trial) {
+                for (int a = 0; a < 7; ++a)
+                    if (hipMemcpyAsync(copy[a], src[a], bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                        rc = fail(c, CC_ERR_DEVICE, "autotune copy");
+                if (rc != CC_OK) break;
+                cc_state w{copy[0], copy[1], copy[2], copy[3], copy[4], copy[5], copy[6]};
+                hipEventRecord(e0, st);
+                rc = cc_evolve(c, &w, n, dt, dt, nullptr, stream);
+                hipEventRecord(e1, st);
+                if (rc != CC_OK) break;
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    rc = fail(c, CC_ERR_DEVICE, "autotune timing");
+                    break;
+                }
+                float ms = 0.0f;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (trial > 0) best_ms = std::min(best_ms, ms);
+            }
+            if (rc != CC_OK) break;
+            best.trials++;
+            if (best_ms < best.ms_per_step) {
+                best.ms_per_step = best_ms;
+                best.small_max = sm;
+                best.sweep_split_tiles = sp;
+            }
+        }
+    }
+    for (auto p : copy)
+        if (p) hipFree(p);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (rc != CC_OK) {
+        const std::string msg = c->err;
+        cc_set_params(c, &keep);
+        c->sweep_split = keep_split;
+        c->err = msg;
+        return rc;
+    }
+    cc_params q = keep;
+    q.small_max = best.small_max;
+    RC(cc_set_params(c, &q));
+    c->sweep_split = best.sweep_split_tiles;
+    if (out) *out = best;
+    return CC_OK;
 }
 
 int cc_evolve_batch(cc_ctx *c, cc_state *s, const int64_t *offsets, int32_t ncl, double dt, double t_end,

@@ -251,11 +251,9 @@ __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg
 // particle whose local root has a different global root into the global
 // structure: at most one global union per particle per tile.
 constexpr int ST = 64;  // sweep tile edge (one wavefront)
-// Launches of few tiles split each tile's partners over JS = 4 wavefronts so
-// that the partner loops are short (up to SWEEP_SPLIT4_TILES tiles; a split
-// in two for mid-size launches measured slower than none).
-constexpr int SWEEP_SPLIT4_TILES = 2048;
-constexpr int SWEEP_SPLIT2_TILES = 2048;
+// Launches of up to split_tiles tiles split each tile's partners over JS = 4
+// wavefronts so that the partner loops are short (the host's tuned value; a
+// split in two for mid-size launches measured slower than none).
 
 // One ST x ST tile of a set's pair triangle per JS wavefronts: wavefront
 // jpart of the tile takes the tile's i particles against its ST/JS partners
@@ -1555,10 +1553,10 @@ hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t 
 }
 
 hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, DevParams p, double h,
-                        bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st)
+                        bool mixed, int split_tiles, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
     if (a.ntiles == 0) return hipSuccess;
-    const int js = a.ntiles <= SWEEP_SPLIT4_TILES ? 4 : a.ntiles <= SWEEP_SPLIT2_TILES ? 2 : 1;
+    const int js = a.ntiles <= split_tiles ? 4 : 1;
     const int tpb = (TPB / ST) / js;  // tiles per block
     const int nb = (a.ntiles + tpb - 1) / tpb;
 #define CC_SWEEP(M, J)                                                                                          \

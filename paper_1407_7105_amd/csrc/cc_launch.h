@@ -59,8 +59,9 @@ hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t st);
 // the kernels' edge test)
 hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, int32_t *cnt, DevParams p,
                        double h, bool screen32, uint64_t *stats, uint64_t *fam, hipStream_t st);
+// split_tiles: launches of at most this many tiles take one block per tile
 hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, DevParams p, double h,
-                        bool screen32, uint64_t *stats, uint64_t *fam, hipStream_t st);
+                        bool screen32, int split_tiles, uint64_t *stats, uint64_t *fam, hipStream_t st);
 // labels and component sizes; with keys/vals the sort keys of the active
 // particles, with count the work-list counters cleared
 hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,

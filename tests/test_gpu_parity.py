@@ -224,6 +224,25 @@ def test_evolve_with_fp32_screen_bitwise():
         assert st[k] == ost[k], (k, st[k], ost[k])
 
 
+def test_autotune_reads_only_and_keeps_exact_results():
+    """The autotuner times its candidates on a copy; afterwards the state is
+    unchanged and the tuned context still integrates bit-identically."""
+    s = synth.plummer(3000, 5, masses="salpeter")
+    p = oracle.Params(eta=0.01)
+    ctx = ctx_for(p)
+    g = State.from_numpy(s)
+    t = ctx.autotune(g, 1 / 64)
+    assert t["small_max"] in (64, 128, 256, 512) and t["sweep_split_tiles"] in (0, 512, 2048, 8192)
+    assert t["trials"] == 16 and t["ms_per_step"] > 0
+    assert_state_equal(g.to_numpy(), s, "autotune input")
+    ref = s.copy()
+    rc, ost = oracle.evolve(ref, 1 / 64, 1 / 64, p)
+    st = ctx.evolve(g, 1 / 64, 1 / 64)
+    assert_state_equal(g.to_numpy(), ref, "after autotune")
+    for k in STAT_KEYS:
+        assert st[k] == ost[k], (k, st[k], ost[k])
+
+
 def test_evolve_plummer256_to_t1_bitwise():
     """The 256-body workload to t = 1 (64 global steps), bit-identical."""
     s = synth.workload(1)
