@@ -661,12 +661,14 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
 }
 
 // One global step on a list of top-level sets (clusters), all at depth 0.
-int global_step(cc_ctx *c, const std::vector<Seg> &top, double dt)
+// Route the top-level sets (clusters): two-particle and small ones into the
+// level-0 work lists (uploaded on the main stream, which is then synchronised:
+// the host vectors must outlive the copies), large ones into `big`.
+int route_top(cc_ctx *c, const std::vector<Seg> &top, std::vector<Seg> &big, int &n_pairs, int n_small[4])
 {
-    // Route top-level sets: small ones straight to the on-chip / pair kernels
-    // through level-0 work lists; large ones to the grid recursion.
-    std::vector<Seg> big, pairs, small[4];
+    std::vector<Seg> pairs, small[4];
     const int sm = small_max(c);
+    big.clear();
     for (const Seg &g : top) {
         if (g.n == 2) pairs.push_back(g);
         else if (g.n <= sm) {
@@ -674,29 +676,101 @@ int global_step(cc_ctx *c, const std::vector<Seg> &top, double dt)
             small[b].push_back(g);
         } else big.push_back(g);
     }
-    if (!pairs.empty() || !small[0].empty() || !small[1].empty() || !small[2].empty() || !small[3].empty()) {
-        // a pseudo-level above 0 holds the routed lists
-        const int k = 0;
-        RC(ensure_level(c, k, 1));
-        Level &lv = c->levels[k];
-        int32_t cnts[8] = {0};
-        cnts[0] = (int)pairs.size();
-        for (int b = 0; b < 4; ++b) cnts[1 + b] = (int)small[b].size();
-        for (int b = 0; b < 8; ++b) lv.h_count[b] = cnts[b];
-        HIPCHK(hipMemcpyAsync(lv.count, lv.h_count, 8 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
-        if (!pairs.empty())
-            HIPCHK(hipMemcpyAsync(lv.pairs, pairs.data(), pairs.size() * sizeof(Seg), hipMemcpyHostToDevice, c->st));
-        for (int b = 0; b < 4; ++b)
-            if (!small[b].empty())
-                HIPCHK(hipMemcpyAsync(lv.small[b], small[b].data(), small[b].size() * sizeof(Seg),
-                                      hipMemcpyHostToDevice, c->st));
-        const int ns[4] = {(int)small[0].size(), (int)small[1].size(), (int)small[2].size(), (int)small[3].size()};
-        RC(run_small_and_pairs(c, k, lv, dt, (int)pairs.size(), ns, c->st));
-        // the host vectors must outlive the async copies
-        HIPCHK(hipStreamSynchronize(c->st));
-    }
+    n_pairs = (int)pairs.size();
+    for (int b = 0; b < 4; ++b) n_small[b] = (int)small[b].size();
+    if (n_pairs + n_small[0] + n_small[1] + n_small[2] + n_small[3] == 0) return CC_OK;
+    RC(ensure_level(c, 0, 1));
+    Level &lv = c->levels[0];
+    lv.h_count[0] = n_pairs;
+    for (int b = 0; b < 4; ++b) lv.h_count[1 + b] = n_small[b];
+    for (int b = 5; b < 8; ++b) lv.h_count[b] = 0;
+    HIPCHK(hipMemcpyAsync(lv.count, lv.h_count, 8 * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+    if (!pairs.empty())
+        HIPCHK(hipMemcpyAsync(lv.pairs, pairs.data(), pairs.size() * sizeof(Seg), hipMemcpyHostToDevice, c->st));
+    for (int b = 0; b < 4; ++b)
+        if (!small[b].empty())
+            HIPCHK(hipMemcpyAsync(lv.small[b], small[b].data(), small[b].size() * sizeof(Seg), hipMemcpyHostToDevice,
+                                  c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return CC_OK;
+}
+
+// One global step on a list of top-level sets (clusters), all at depth 0.
+int global_step(cc_ctx *c, const std::vector<Seg> &top, double dt)
+{
+    std::vector<Seg> big;
+    int n_pairs = 0, n_small[4] = {0, 0, 0, 0};
+    RC(route_top(c, top, big, n_pairs, n_small));
+    if (n_pairs + n_small[0] + n_small[1] + n_small[2] + n_small[3] > 0)
+        RC(run_small_and_pairs(c, 0, c->levels[0], dt, n_pairs, n_small, c->st));
     if (!big.empty()) RC(evolve_grid(c, 0, big, dt));
     return CC_OK;
+}
+
+// Global steps of sets that are all evolved on chip (an ensemble of small
+// clusters): the device work of one step -- error reset, validation,
+// snapshot, the on-chip launch, validation, error read-back -- is captured once
+// as a HIP graph on the side stream and replayed per step, with one host
+// synchronisation per step for the error check.  *done = steps completed;
+// *captured = false if the graph could not be built (nothing has run then, and
+// the caller takes the steps one launch at a time).
+int evolve_on_chip_graph(cc_ctx *c, const std::vector<Seg> &top, int64_t n, int64_t nsteps, double dt,
+                         int64_t *done, bool *captured)
+{
+    *captured = false;
+    std::vector<Seg> big;
+    int n_pairs = 0, n_small[4] = {0, 0, 0, 0};
+    RC(route_top(c, top, big, n_pairs, n_small));  // also orders the caller's copies before the graph
+    const int mode = mixed(c) ? 2 : (exact_order(c) ? 1 : 0);
+    HIPCHK(configure_items(small_max(c), mode));
+    const size_t bytes = (size_t)n * sizeof(double);
+    hipStream_t g = c->side;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIPCHK(hipStreamBeginCapture(g, hipStreamCaptureModeThreadLocal));
+    int rc = CC_OK;
+    {
+        const bool ok = launch_fill_i32(c->errf, 1, 0, g) == hipSuccess &&
+                        launch_validate(c->w[0], c->w[1], c->w[2], c->w[3], c->w[4], c->w[5], c->w[6], n, c->errf,
+                                        g) == hipSuccess;
+        if (!ok) rc = fail(c, CC_ERR_DEVICE, "graph capture of the step prologue failed");
+        for (int a = 0; a < 6 && rc == CC_OK; ++a)
+            if (hipMemcpyAsync(c->snap[a], c->w[a], bytes, hipMemcpyDeviceToDevice, g) != hipSuccess)
+                rc = fail(c, CC_ERR_DEVICE, "graph capture of the snapshot failed");
+        if (rc == CC_OK) rc = run_small_and_pairs(c, 0, c->levels[0], dt, n_pairs, n_small, g);
+        if (rc == CC_OK &&
+            (launch_validate(c->w[0], c->w[1], c->w[2], c->w[3], c->w[4], c->w[5], c->w[6], n, c->errf, g) !=
+                 hipSuccess ||
+             hipMemcpyAsync(c->h_err, c->errf, sizeof(int32_t), hipMemcpyDeviceToHost, g) != hipSuccess))
+            rc = fail(c, CC_ERR_DEVICE, "graph capture of the step epilogue failed");
+    }
+    const hipError_t ec = hipStreamEndCapture(g, &graph);
+    if (rc == CC_OK && ec != hipSuccess) rc = fail(c, CC_ERR_DEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+    if (rc == CC_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+        rc = fail(c, CC_ERR_DEVICE, "hipGraphInstantiate failed");
+    if (rc != CC_OK) {
+        if (graph) hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        c->err.clear();
+        return CC_OK;
+    }
+    *captured = true;
+    for (int64_t step = 0; step < nsteps && rc == CC_OK; ++step) {
+        if (hipGraphLaunch(exec, g) != hipSuccess || hipStreamSynchronize(g) != hipSuccess) {
+            rc = fail(c, CC_ERR_DEVICE, "graph replay failed");
+            break;
+        }
+        if (*c->h_err) {
+            rc = err_code(c, *c->h_err);
+            for (int a = 0; a < 6; ++a) hipMemcpyAsync(c->w[a], c->snap[a], bytes, hipMemcpyDeviceToDevice, g);
+            hipStreamSynchronize(g);
+            break;
+        }
+        *done = step + 1;
+    }
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    return rc;
 }
 
 int check_state_ptrs(cc_ctx *c, const cc_state *s)
@@ -742,6 +816,13 @@ int evolve_common(cc_ctx *c, cc_state *s, int64_t n, const int64_t *off, int32_t
     HIPCHK(launch_iota(c->orig, n, c->st));
     int rc = CC_OK;
     int64_t done = 0;
+    bool all_on_chip = true;
+    for (const Seg &g : top) all_on_chip = all_on_chip && g.n <= small_max(c);
+    if (all_on_chip && nsteps >= 2 && !c->timing) {
+        bool captured = false;
+        rc = evolve_on_chip_graph(c, top, n, nsteps, dt, &done, &captured);
+        if (captured || rc != CC_OK) nsteps = 0;  // the loop below has nothing left to do
+    }
     for (int64_t step = 0; step < nsteps; ++step) {
         HIPCHK(launch_fill_i32(c->errf, 1, 0, c->st));
         {

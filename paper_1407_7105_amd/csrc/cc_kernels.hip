@@ -1688,17 +1688,28 @@ hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, c
     return hipGetLastError();
 }
 
+// LDS limit of k_items<CAP, MODE>, set once per process (before any capture)
 template <int CAP, int MODE>
-static hipError_t launch_items_cap(SoA W, const SmallArgs &s, int nbp, int nbb, int nbw, double H, DevParams p,
-                                   int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
+static hipError_t configure_items_cap(size_t lds)
 {
     static bool configured = false;
-    const size_t lds = std::max(sizeof(SmallLDS<CAP>), sizeof(SmallLDS<SMALL_WAVE_CAP>) * (TPB / WAVE));
     if (!configured) {
         hipError_t e = hipFuncSetAttribute((const void *)k_items<CAP, MODE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         configured = true;
+    }
+    return hipSuccess;
+}
+
+template <int CAP, int MODE>
+static hipError_t launch_items_cap(SoA W, const SmallArgs &s, int nbp, int nbb, int nbw, double H, DevParams p,
+                                   int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
+{
+    const size_t lds = std::max(sizeof(SmallLDS<CAP>), sizeof(SmallLDS<SMALL_WAVE_CAP>) * (TPB / WAVE));
+    {
+        hipError_t e = configure_items_cap<CAP, MODE>(lds);
+        if (e != hipSuccess) return e;
     }
     SmallItems it{};
     for (int b = 0; b < 4; ++b) it.bin[b] = s.bin[b];
@@ -1716,6 +1727,16 @@ size_t items_lds_bytes(int cap)
     if (cap <= 256) return std::max(sizeof(SmallLDS<256>), w);
     if (cap <= 512) return std::max(sizeof(SmallLDS<512>), w);
     return std::max(sizeof(SmallLDS<1024>), w);
+}
+
+hipError_t configure_items(int cap, int mode)
+{
+#define CC_CONF(C, M) configure_items_cap<C, M>(std::max(sizeof(SmallLDS<C>), sizeof(SmallLDS<SMALL_WAVE_CAP>) * (TPB / WAVE)))
+    const int c = cap <= 256 ? 256 : cap <= 512 ? 512 : 1024;
+    if (c == 256) return mode == 1 ? CC_CONF(256, 1) : mode == 2 ? CC_CONF(256, 2) : CC_CONF(256, 0);
+    if (c == 512) return mode == 1 ? CC_CONF(512, 1) : mode == 2 ? CC_CONF(512, 2) : CC_CONF(512, 0);
+    return mode == 1 ? CC_CONF(1024, 1) : mode == 2 ? CC_CONF(1024, 2) : CC_CONF(1024, 0);
+#undef CC_CONF
 }
 
 hipError_t launch_items(SoA W, const SmallArgs &s, int cap, int mode, int nbp, int nbb, int nbw, double H,

@@ -92,6 +92,9 @@ hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, c
 // cap = largest size), nbw blocks of bins 0-1 (one per wavefront).
 // mode: 0 = FP64 slot order, 1 = FP64 ascending index order, 2 = mixed.
 size_t items_lds_bytes(int cap);
+// sets the kernel's LDS limit (host-side, once per process); launch_items does
+// it on first use, a graph capture needs it done before
+hipError_t configure_items(int cap, int mode);
 hipError_t launch_items(SoA W, const SmallArgs &s, int cap, int mode, int nbp, int nbb, int nbw, double H,
                         DevParams p, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
 int diag_blocks(int n);
