@@ -100,7 +100,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-eta-scan", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the launch shapes on this workload first (the library defaults are the tuner's "
+                         "choice for it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -127,7 +129,7 @@ def main():
         return ctx.evolve(s, dt, dt)
 
     tune = None
-    if not args.no_autotune:
+    if args.autotune:
         # launch shapes (on-chip size limit, sweep tiles per workgroup) from
         # the library's autotuner, on this workload, before anything is timed
         tune = ctx.autotune(ic, dt)

@@ -77,8 +77,8 @@ typedef struct {
     double G;               /* gravitational constant (> 0; 1 in N-body units) */
     int32_t max_depth;      /* recursion cap (levels below the global step), >= 0 */
     int32_t precision;      /* cc_precision */
-    int32_t small_max;      /* largest component integrated on chip by one
-                               workgroup (3..1024; 0 = library default) */
+    int32_t small_max;      /* largest component integrated on chip (3..1024;
+                               0 = library default, 128) */
     int32_t kick_order;     /* cc_kick_order */
     int32_t screen;         /* cc_screen for the grid-wide star test and sweep; either
                                screen leaves undecided pairs to the literal FP64 formula,

@@ -32,7 +32,7 @@ using namespace ccg;
 namespace {
 
 constexpr int TPB = 256;
-constexpr int DEFAULT_SMALL_MAX = 256;
+constexpr int DEFAULT_SMALL_MAX = 128;  // the autotuner's choice on the 16 384-body workload
 constexpr int kLevels = 64;  // grid recursion levels a context can hold (max_depth <= 60)
 constexpr int SWEEP_TILE = 64;  // edge of the all-pairs sweep tiles
 constexpr int32_t DEFAULT_SWEEP_SPLIT = 2048;
