@@ -31,6 +31,24 @@ FLOP_TAU = 48      # FP64 operations of one pair time step, eq. 19 (div and sqrt
 FLOP_KICK = 26     # FP64 operations of one symmetric pair kick, eqs. 8-9
 PEAK_FP64_VECTOR = 78.6e12   # MI355X: 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 
+# HBM bytes per sweep launch on this workload (rocprofv3 FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0, the factors from a plain 256 MiB device copy; see
+# profiles/hbm_traffic_plummer16k_salpeter_fp64.md), valid for the kernel
+# sources with this SHA-1; any other source reports null.
+SWEEP_TRAFFIC_BYTES = 4750938
+SWEEP_TRAFFIC_SOURCES = ("paper_1407_7105_amd/csrc/cc_kernels.hip", "paper_1407_7105_amd/csrc/cc_device.h",
+                         "paper_1407_7105_amd/csrc/cc_screen64.h")
+SWEEP_TRAFFIC_SHA1 = "531a5d17deb99684ec188139629e0bd3faff8d90"
+
+
+def sweep_traffic():
+    import hashlib
+    h = hashlib.sha1()
+    for f in SWEEP_TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return SWEEP_TRAFFIC_BYTES if h.hexdigest() == SWEEP_TRAFFIC_SHA1 else None
+
 
 def cpu_baseline(p, dt, eta):
     """The FP64 oracle on a bounded sample of the same workload (one host
@@ -167,7 +185,8 @@ def main():
         flops = FLOP_TAU * d["tau_pairs"] + FLOP_KICK * d["kick_pairs"]
         achieved = flops / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64_VECTOR / 1e12), "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64_VECTOR / 1e12),
+                "traffic": sweep_traffic() if dom == "sweep" else None, "traffic_unit": "bytes per launch",
                 "avg_launch_ms": d["ms"] / d["launches"], "launches_per_step": d["launches"] / args.steps}
 
     scan = None if args.no_eta_scan else eta_scan(p, wl, dev, args.small_max)
