@@ -168,18 +168,19 @@ int cc_evolve_batch(cc_ctx *ctx, cc_state *s, const int64_t *offsets, int32_t nc
  * mass.  Syncs. */
 int cc_diagnostics(cc_ctx *ctx, const cc_state *s, int64_t n, double *out, void *stream);
 
-/* Autotuner for the launch shapes of the batched recursion (persistent
- * on-chip kernel and sweep tiles).  Times one global step of the given state
- * (device SoA as for cc_evolve; only read: every trial runs on a copy) for
- * each candidate of the largest component run on chip (small_max in
- * {64, 128, 256, 512}) and of the sweep launches that give each tile a whole
- * workgroup (up to {0, 512, 2048, 8192} tiles), keeps the fastest in the
- * context (params.small_max is overwritten) and reports it in *out (may be
- * NULL).  Partitions and results in the EXACT kick order do not depend on the
- * choice.  Allocates a copy of the state; syncs. */
+/* Autotuner for the launch shapes of the batched recursion.  Times one global
+ * step of the given state (device SoA as for cc_evolve; only read: every trial
+ * runs on a copy) while it varies, one at a time from the best so far, the
+ * largest component run on chip (small_max in {64, 128, 256, 512}), the sweep
+ * launches that give each tile a whole workgroup (up to {0, 512, 2048, 8192}
+ * tiles) and the kick blocks per compute unit ({2, 4, 8, 16}); keeps the
+ * fastest in the context (params.small_max is overwritten) and reports it in
+ * *out (may be NULL).  Partitions and results in the EXACT kick order do not
+ * depend on the choice.  Allocates a copy of the state; syncs. */
 typedef struct {
     int32_t small_max;          /* chosen on-chip size limit */
     int32_t sweep_split_tiles;  /* chosen: sweep launches up to this many tiles use one workgroup per tile */
+    int32_t kick_groups_per_cu; /* chosen: kick launches aim at this many blocks per compute unit */
     double ms_per_step;         /* best time of one global step with the choice */
     int32_t trials;             /* configurations timed */
 } cc_tune;

@@ -43,8 +43,8 @@ class _Stats(C.Structure):
 
 
 class _Tune(C.Structure):
-    _fields_ = [("small_max", C.c_int32), ("sweep_split_tiles", C.c_int32), ("ms_per_step", C.c_double),
-                ("trials", C.c_int32)]
+    _fields_ = [("small_max", C.c_int32), ("sweep_split_tiles", C.c_int32), ("kick_groups_per_cu", C.c_int32),
+                ("ms_per_step", C.c_double), ("trials", C.c_int32)]
 
 
 class _KTime(C.Structure):
@@ -241,8 +241,8 @@ class Context:
         t = _Tune()
         self._check(self._L.cc_autotune(self._h, C.byref(s._c()), s.n, dt, C.byref(t), _stream()))
         self._p.small_max = t.small_max
-        return dict(small_max=t.small_max, sweep_split_tiles=t.sweep_split_tiles, ms_per_step=t.ms_per_step,
-                    trials=t.trials)
+        return dict(small_max=t.small_max, sweep_split_tiles=t.sweep_split_tiles,
+                    kick_groups_per_cu=t.kick_groups_per_cu, ms_per_step=t.ms_per_step, trials=t.trials)
 
     def timing(self, enable: bool):
         self._check(self._L.cc_timing_enable(self._h, 1 if enable else 0))

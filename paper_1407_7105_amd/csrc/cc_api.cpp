@@ -36,6 +36,7 @@ constexpr int DEFAULT_SMALL_MAX = 128;  // the autotuner's choice on the 16 384-
 constexpr int kLevels = 64;  // grid recursion levels a context can hold (max_depth <= 60)
 constexpr int SWEEP_TILE = 64;  // edge of the all-pairs sweep tiles
 constexpr int32_t DEFAULT_SWEEP_SPLIT = 2048;
+constexpr int32_t DEFAULT_KICK_GROUPS = 8;
 
 // kernel families for timing
 enum Fam { F_STAR, F_SWEEP, F_LABEL, F_SORT, F_PERMUTE, F_DRIFT, F_KICK, F_PAIRS, F_SMALL, F_VALIDATE, F_OTHER, F_N };
@@ -106,6 +107,7 @@ struct cc_ctx {
     int32_t *qhead = nullptr;    // per level: head and blocks finished of the workgroup and the wavefront queues
     int32_t epoch = 0;           // visit counter for the non-star flags
     int32_t sweep_split = DEFAULT_SWEEP_SPLIT;  // sweep launches up to this many tiles: one block per tile
+    int32_t kick_groups = DEFAULT_KICK_GROUPS;  // kick launches aim at this many blocks per compute unit
     double *kick_acc = nullptr;  // 3*cap for cc_kick
     double *kick_part = nullptr; // partial accelerations of the tiled kick
     size_t kick_part_cap = 0;    // in kick blocks
@@ -506,7 +508,7 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     int64_t totT = 0;
     for (int s = 0; s < nseg; ++s) totT += (segs[s].n + TPB - 1) / TPB;
     // enough (i tile, j group) blocks to fill the chip several times over
-    const int64_t gtarget = std::max<int64_t>(1, (8 * (int64_t)c->cus + totT - 1) / totT);
+    const int64_t gtarget = std::max<int64_t>(1, ((int64_t)c->kick_groups * c->cus + totT - 1) / totT);
     for (int s = 0; s < nseg; ++s) {
         lv.h_seg[s] = segs[s];
         const int n = segs[s].n;
@@ -575,6 +577,13 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         Span s(c, F_PERMUTE);
         HIPCHK(launch_permute(W, T, a, lv.src, lv.label, c->cnt, lv.sing, &L, c->stats, false, c->st));
     }
+    if (!exact) {
+        // The singletons' first drift touches no particle of a component, so
+        // it may precede the first-half recursion: queued before the host
+        // waits for the report, it runs while the host reads it.
+        Span s(c, F_DRIFT);
+        HIPCHK(launch_drift_seg(W, a, lv.singp, 0.5 * h, c->stats, c->st));
+    }
     HIPCHK(hipMemcpyAsync(lv.h_rep, lv.rep, 8 * sizeof(int32_t) + (size_t)lv.cap_big * sizeof(Seg),
                           hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
@@ -598,14 +607,11 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     }
 
     if (!exact) {
-        // Component-contiguous order throughout: first half, drift/kick/drift
-        // of the level, second half, then back to the entry order.
+        // Component-contiguous order throughout: (the first drift, queued
+        // above), first half, kick and closing drift of the level, second
+        // half, then back to the entry order.
         if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
         Level &lv2 = c->levels[k];
-        {
-            Span s(c, F_DRIFT);
-            HIPCHK(launch_drift_seg(W, a, lv2.singp, H, c->stats, c->st));
-        }
         {
             // the kick, then the second drift of the singletons (fused)
             Span s(c, F_KICK);
@@ -1091,43 +1097,55 @@ int cc_autotune(cc_ctx *c, const cc_state *s, int64_t n, double dt, cc_tune *out
     if (rc == CC_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess))
         rc = fail(c, CC_ERR_DEVICE, "autotune events");
     const cc_params keep = c->params;
-    const int32_t keep_split = c->sweep_split;
-    cc_tune best{keep.small_max, keep_split, 1e300, 0};
+    const int32_t keep_split = c->sweep_split, keep_kg = c->kick_groups;
+    cc_tune best{small_max(c), c->sweep_split, c->kick_groups, 1e300, 0};
+    // one untimed step (buffers sized for the setting), then the best of two
+    auto time_step = [&](double *ms_out) -> int {
+        float best_ms = 1e30f;
+        for (int trial = 0; trial < 3; ++trial) {
+            for (int a = 0; a < 7; ++a)
+                if (hipMemcpyAsync(copy[a], src[a], bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
+                    return fail(c, CC_ERR_DEVICE, "autotune copy");
+            cc_state w{copy[0], copy[1], copy[2], copy[3], copy[4], copy[5], copy[6]};
+            hipEventRecord(e0, st);
+            RC(cc_evolve(c, &w, n, dt, dt, nullptr, stream));
+            hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) return fail(c, CC_ERR_DEVICE, "autotune timing");
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (trial > 0) best_ms = std::min(best_ms, ms);
+        }
+        *ms_out = best_ms;
+        return CC_OK;
+    };
+    auto apply = [&](const cc_tune &t) -> int {
+        cc_params q = keep;
+        q.small_max = t.small_max;
+        RC(cc_set_params(c, &q));
+        c->sweep_split = t.sweep_split_tiles;
+        c->kick_groups = t.kick_groups_per_cu;
+        return CC_OK;
+    };
+    // coordinate descent over the three shapes, each from the best so far
     const int32_t sm_cand[] = {64, 128, 256, 512};
     const int32_t split_cand[] = {0, 512, 2048, 8192};
-    for (int32_t sm : sm_cand) {
-        if (rc != CC_OK) break;
-        cc_params q = keep;
-        q.small_max = sm;
-        if ((rc = cc_set_params(c, &q)) != CC_OK) break;
-        for (int32_t sp : split_cand) {
-            c->sweep_split = sp;
-            float best_ms = 1e30f;
-            // one untimed step (buffers sized for this setting), then two timed
-            for (int trial = 0; trial < 3 && rc == CC_OK; ++trial) {
-                for (int a = 0; a < 7; ++a)
-                    if (hipMemcpyAsync(copy[a], src[a], bytes, hipMemcpyDeviceToDevice, st) != hipSuccess)
-                        rc = fail(c, CC_ERR_DEVICE, "autotune copy");
-                if (rc != CC_OK) break;
-                cc_state w{copy[0], copy[1], copy[2], copy[3], copy[4], copy[5], copy[6]};
-                hipEventRecord(e0, st);
-                rc = cc_evolve(c, &w, n, dt, dt, nullptr, stream);
-                hipEventRecord(e1, st);
-                if (rc != CC_OK) break;
-                if (hipEventSynchronize(e1) != hipSuccess) {
-                    rc = fail(c, CC_ERR_DEVICE, "autotune timing");
-                    break;
-                }
-                float ms = 0.0f;
-                hipEventElapsedTime(&ms, e0, e1);
-                if (trial > 0) best_ms = std::min(best_ms, ms);
-            }
-            if (rc != CC_OK) break;
+    const int32_t kg_cand[] = {2, 4, 8, 16};
+    for (int knob = 0; knob < 3 && rc == CC_OK; ++knob) {
+        const int32_t *cand = knob == 0 ? sm_cand : knob == 1 ? split_cand : kg_cand;
+        cc_tune base = best;
+        for (int i = 0; i < 4 && rc == CC_OK; ++i) {
+            cc_tune t = base;
+            if (knob == 0) t.small_max = cand[i];
+            else if (knob == 1) t.sweep_split_tiles = cand[i];
+            else t.kick_groups_per_cu = cand[i];
+            double ms = 0.0;
+            if ((rc = apply(t)) != CC_OK || (rc = time_step(&ms)) != CC_OK) break;
             best.trials++;
-            if (best_ms < best.ms_per_step) {
-                best.ms_per_step = best_ms;
-                best.small_max = sm;
-                best.sweep_split_tiles = sp;
+            if (ms < best.ms_per_step) {
+                const int32_t trials = best.trials;
+                best = t;
+                best.ms_per_step = ms;
+                best.trials = trials;
             }
         }
     }
@@ -1139,13 +1157,11 @@ int cc_autotune(cc_ctx *c, const cc_state *s, int64_t n, double dt, cc_tune *out
         const std::string msg = c->err;
         cc_set_params(c, &keep);
         c->sweep_split = keep_split;
+        c->kick_groups = keep_kg;
         c->err = msg;
         return rc;
     }
-    cc_params q = keep;
-    q.small_max = best.small_max;
-    RC(cc_set_params(c, &q));
-    c->sweep_split = best.sweep_split_tiles;
+    RC(apply(best));
     if (out) *out = best;
     return CC_OK;
 }
