@@ -225,7 +225,7 @@ int ensure_capacity(cc_ctx *c, size_t n, size_t ncl)
         RC(dalloc(c, &c->keys, cap));
         RC(dalloc(c, &c->keys_out, cap));
         RC(dalloc(c, &c->vals, cap));
-        RC(dalloc(c, &c->parent, cap));
+        RC(dalloc(c, &c->parent, cap * PARENT_STRIDE));  // one entry per 128-byte line
         RC(dalloc(c, &c->cnt, cap));
         RC(dalloc(c, &c->kick_acc, 3 * cap));
         size_t sb = sort_temp_bytes((int)cap);

@@ -49,6 +49,12 @@ constexpr uint64_t PAIR_LEAF_BUDGET = 1ull << 28;
 constexpr uint64_t ITEM_VISIT_BUDGET = 1ull << 24;
 constexpr int FIND_BUDGET = 1 << 22;
 
+// The global union-find keeps one parent entry per 128-byte line: its
+// coherent loads, path-halving stores and compare-and-swaps come from every
+// tile of a sweep at once, and packed entries would make a few hundred lines
+// the serialisation point of the whole launch (slot a lives at a * stride).
+constexpr int PARENT_STRIDE = 32;
+
 // Working state: structure of arrays plus the original particle index.
 struct SoA {
     double *x, *y, *z, *vx, *vy, *vz, *m;

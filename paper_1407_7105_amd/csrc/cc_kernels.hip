@@ -65,7 +65,8 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh)
 }
 
 // ---------------------------------------------------------------------------
-// Global union-find helpers (parent array in global memory, L1 bypassed).
+// Global union-find helpers (parent array in global memory, L1 bypassed,
+// one entry per PARENT_STRIDE ints).
 // The smaller root always becomes the parent, so a tree's root is its
 // smallest slot and the final label is the component's smallest slot.
 // ---------------------------------------------------------------------------
@@ -81,13 +82,15 @@ __device__ __forceinline__ void gstore(int32_t *p, int32_t v)
 
 // Parent pointers only ever point to smaller slots, so a walk ends within
 // the segment size; the budget only guards against corrupted input.
+__device__ __forceinline__ int32_t *pslot(int32_t *par, int32_t a) { return par + (size_t)a * PARENT_STRIDE; }
+
 __device__ __forceinline__ int32_t gfind(int32_t *par, int32_t a)
 {
     for (int it = 0; it < FIND_BUDGET; ++it) {
-        const int32_t q = gload(&par[a]);
+        const int32_t q = gload(pslot(par, a));
         if (q == a) return a;
-        const int32_t g = gload(&par[q]);
-        if (g != q) gstore(&par[a], g);  // path halving: g is an ancestor of a
+        const int32_t g = gload(pslot(par, q));
+        if (g != q) gstore(pslot(par, a), g);  // path halving: g is an ancestor of a
         a = q;
     }
     return a;
@@ -104,7 +107,7 @@ __device__ __forceinline__ int32_t gunite(int32_t *par, int32_t a, int32_t b)
             a = b;
             b = t;
         }
-        if (atomicCAS(&par[b], b, a) == b) return a;
+        if (atomicCAS(pslot(par, b), b, a) == b) return a;
     }
     return a;
 }
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg
     uint64_t ev = 0;
     if (local < g.n) {
         const int u = g.start + local;
-        parent[u] = u;
+        *pslot(parent, u) = u;
         cnt[u] = 0;
         if (local > 0) {
             ev = 1;
