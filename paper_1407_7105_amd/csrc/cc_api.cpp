@@ -36,7 +36,7 @@ constexpr int DEFAULT_SMALL_MAX = 128;  // the autotuner's choice on the 16 384-
 constexpr int kLevels = 64;  // grid recursion levels a context can hold (max_depth <= 60)
 constexpr int SWEEP_TILE = 64;  // edge of the all-pairs sweep tiles
 constexpr int32_t DEFAULT_SWEEP_SPLIT = 2048;
-constexpr int32_t DEFAULT_KICK_GROUPS = 8;
+constexpr int32_t DEFAULT_KICK_GROUPS = 4;
 
 // kernel families for timing
 enum Fam { F_STAR, F_SWEEP, F_LABEL, F_SORT, F_PERMUTE, F_DRIFT, F_KICK, F_PAIRS, F_SMALL, F_VALIDATE, F_OTHER, F_N };
@@ -64,11 +64,18 @@ struct Level {
     int32_t *count = nullptr, *h_count = nullptr;
     Seg *big = nullptr, *h_big = nullptr;
     // Descriptor block, uploaded with one copy per visit: nseg segments
-    // followed by 5 arrays of nseg+1 ints (chunk, tile, act, kick prefixes,
-    // kick groups).
+    // followed by 3 arrays of nseg+1 ints (chunk, tile and slot prefixes).
     unsigned char *desc = nullptr, *h_desc = nullptr;
     Seg *seg = nullptr, *h_seg = nullptr;
     int32_t *offs = nullptr, *h_offs = nullptr;
+    // Kick list, uploaded once the level's components are known: one
+    // KickTile per i tile followed by the KickBlocks.  kick_ev marks the end
+    // of the last upload from h_kick, which the next visit must not overwrite
+    // before.
+    unsigned char *kick = nullptr, *h_kick = nullptr;
+    size_t cap_kick = 0;  // bytes
+    hipEvent_t kick_ev = nullptr;
+    bool kick_pending = false;
     int cap_big = 0, cap_small = 0, cap_pairs = 0;
 };
 
@@ -111,6 +118,7 @@ struct cc_ctx {
     double *kick_acc = nullptr;  // 3*cap for cc_kick
     double *kick_part = nullptr; // partial accelerations of the tiled kick
     size_t kick_part_cap = 0;    // in kick blocks
+    std::vector<int32_t> kick_scratch;  // host scratch of the kick-list builder
     double *diag_part = nullptr;
     size_t diag_cap = 0;
     double *diag_out = nullptr, *h_diag = nullptr;
@@ -278,7 +286,7 @@ int ensure_level(cc_ctx *c, int k, size_t nseg)
         RC(dalloc(c, &lv.notstar, cs));
         // no stale flag may equal a later visit's epoch
         HIPCHK(hipMemset(lv.notstar, 0, cs * sizeof(int32_t)));
-        const size_t bytes = cs * sizeof(Seg) + 5 * (cs + 1) * sizeof(int32_t);
+        const size_t bytes = cs * sizeof(Seg) + 3 * (cs + 1) * sizeof(int32_t);
         RC(dalloc(c, &lv.desc, bytes));
         RC(halloc(c, &lv.h_desc, bytes));
         lv.seg = reinterpret_cast<Seg *>(lv.desc);
@@ -419,7 +427,7 @@ void place_offsets(Level &lv, int nseg)
 
 int upload_desc(cc_ctx *c, Level &lv, int nseg)
 {
-    const size_t bytes = (size_t)nseg * sizeof(Seg) + 5 * ((size_t)nseg + 1) * sizeof(int32_t);
+    const size_t bytes = (size_t)nseg * sizeof(Seg) + 3 * ((size_t)nseg + 1) * sizeof(int32_t);
     HIPCHK(hipMemcpyAsync(lv.desc, lv.h_desc, bytes, hipMemcpyHostToDevice, c->st));
     return CC_OK;
 }
@@ -454,6 +462,93 @@ int run_small_and_pairs(cc_ctx *c, int k, Level &lv, double H, int n_pairs, cons
 }
 
 int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h);
+
+// Kick blocks of one level visit, in the component-contiguous order: every
+// 256-slot i tile sees its whole segment, except that a tile lying inside one
+// large component leaves that component out (all of its pairs are inside it).
+// The j ranges are cut into chunks of cj partners, a multiple of KICK_JW
+// chosen so that the launch has about kick_groups blocks per compute unit of
+// equal work, wherever in the segments the work lies.  The list (a KickTile
+// per i tile, then the blocks) goes up with one copy on the main stream, and
+// the partial-acceleration buffer grows to the block count.
+int upload_kick_list(cc_ctx *c, Level &lv, const std::vector<Seg> &segs, const std::vector<Seg> &big, int *nblk_out)
+{
+    // per i tile, the partners [xlo, xhi) it leaves out (offsets within the
+    // segment; empty when xlo == xhi)
+    std::vector<int32_t> &tr = c->kick_scratch;
+    tr.clear();
+    int64_t work = 0;
+    size_t bi = 0;  // big is sorted by start; segments come in slot order
+    for (const Seg &g : segs) {
+        const int T = (g.n + TPB - 1) / TPB;
+        for (int I = 0; I < T; ++I) {
+            const int lo = g.start + I * TPB, hi = g.start + std::min(g.n, (I + 1) * TPB);
+            while (bi < big.size() && big[bi].start + big[bi].n <= lo) ++bi;
+            int32_t xlo = 0, xhi = 0;
+            if (bi < big.size() && big[bi].start <= lo && hi <= big[bi].start + big[bi].n) {
+                xlo = big[bi].start - g.start;
+                xhi = big[bi].start + big[bi].n - g.start;
+            }
+            tr.push_back(xlo);
+            tr.push_back(xhi);
+            work += (int64_t)(hi - lo) * (g.n - (xhi - xlo));
+        }
+    }
+    const int64_t target = std::max<int64_t>(1, (int64_t)c->kick_groups * c->cus);
+    int64_t cj = (work + target * TPB - 1) / (target * TPB);
+    cj = std::max<int64_t>(KICK_JW, (cj + KICK_JW - 1) / KICK_JW * KICK_JW);
+    const auto nchunk = [cj](int64_t len) { return len > 0 ? (len + cj - 1) / cj : 0; };
+    int64_t nblk = 0;
+    {
+        size_t t = 0;
+        for (const Seg &g : segs)
+            for (int I = 0; I < (g.n + TPB - 1) / TPB; ++I, ++t) nblk += nchunk(tr[2 * t]) + nchunk(g.n - tr[2 * t + 1]);
+    }
+    if (nblk > INT32_MAX) return fail(c, CC_ERR_ARG, "kick list too long");
+    const size_t ntile = tr.size() / 2;
+    const size_t bytes = ntile * sizeof(KickTile) + (size_t)nblk * sizeof(KickBlock);
+    if (lv.kick_pending) {
+        HIPCHK(hipEventSynchronize(lv.kick_ev));
+        lv.kick_pending = false;
+    }
+    if (bytes > lv.cap_kick || (size_t)nblk > c->kick_part_cap) {
+        // buffers still read by queued kicks: let both streams drain first
+        HIPCHK(hipStreamSynchronize(c->st));
+        HIPCHK(hipStreamSynchronize(c->side));
+        if (bytes > lv.cap_kick) {
+            const size_t cap = std::max(bytes, 2 * lv.cap_kick);
+            RC(dalloc(c, &lv.kick, cap));
+            RC(halloc(c, &lv.h_kick, cap));
+            lv.cap_kick = cap;
+        }
+        if ((size_t)nblk > c->kick_part_cap) {
+            const size_t cap = std::max((size_t)nblk, 2 * c->kick_part_cap);
+            RC(dalloc(c, &c->kick_part, cap * 3 * TPB));
+            c->kick_part_cap = cap;
+        }
+    }
+    if (!lv.kick_ev) HIPCHK(hipEventCreateWithFlags(&lv.kick_ev, hipEventDisableTiming));
+    KickTile *kt = reinterpret_cast<KickTile *>(lv.h_kick);
+    KickBlock *kb = reinterpret_cast<KickBlock *>(lv.h_kick + ntile * sizeof(KickTile));
+    int32_t b = 0;
+    size_t t = 0;
+    for (int s = 0; s < (int)segs.size(); ++s) {
+        const Seg &g = segs[s];
+        for (int I = 0; I < (g.n + TPB - 1) / TPB; ++I, ++t) {
+            kt[t].b0 = b;
+            const int32_t ranges[2][2] = {{0, tr[2 * t]}, {tr[2 * t + 1], g.n}};
+            for (const auto &r : ranges)
+                for (int64_t j0 = r[0]; j0 < r[1]; j0 += cj)
+                    kb[b++] = KickBlock{s, I, (int32_t)j0, (int32_t)std::min<int64_t>(cj, r[1] - j0)};
+            kt[t].nb = b - kt[t].b0;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(lv.kick, lv.h_kick, bytes, hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipEventRecord(lv.kick_ev, c->st));
+    lv.kick_pending = true;
+    *nblk_out = (int)nblk;
+    return CC_OK;
+}
 
 // Items of one list of independent sets at level depth: route by size.
 // The on-chip components of a level and its large components are disjoint
@@ -502,37 +597,23 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     // segment descriptors and prefix arrays
     const size_t S1 = (size_t)nseg + 1;
     place_offsets(lv, nseg);
-    int32_t *chunk = lv.h_offs, *tile = lv.h_offs + S1, *act = lv.h_offs + 2 * S1, *koff = lv.h_offs + 3 * S1,
-            *kgrp = lv.h_offs + 4 * S1;
-    chunk[0] = tile[0] = act[0] = koff[0] = 0;
-    int64_t totT = 0;
-    for (int s = 0; s < nseg; ++s) totT += (segs[s].n + TPB - 1) / TPB;
-    // enough (i tile, j group) blocks to fill the chip several times over
-    const int64_t gtarget = std::max<int64_t>(1, ((int64_t)c->kick_groups * c->cus + totT - 1) / totT);
+    int32_t *chunk = lv.h_offs, *tile = lv.h_offs + S1, *act = lv.h_offs + 2 * S1;
+    chunk[0] = tile[0] = act[0] = 0;
     for (int s = 0; s < nseg; ++s) {
         lv.h_seg[s] = segs[s];
         const int n = segs[s].n;
         const int64_t T = (n + TPB - 1) / TPB;
-        // j groups of at least 32 partners: small sets get short, parallel
-        // partner loops instead of one long one
-        const int64_t G = std::min<int64_t>((n + 31) / 32, gtarget);
         const int64_t T64 = (n + SWEEP_TILE - 1) / SWEEP_TILE;
-        const int64_t nt = tile[s] + T64 * (T64 + 1) / 2, nk = koff[s] + T * G;
-        if (nt > INT32_MAX || nk > INT32_MAX) return fail(c, CC_ERR_ARG, "set of %d particles is too large", n);
+        const int64_t nt = tile[s] + T64 * (T64 + 1) / 2;
+        if (nt > INT32_MAX) return fail(c, CC_ERR_ARG, "set of %d particles is too large", n);
         chunk[s + 1] = chunk[s] + (int32_t)T;
         tile[s + 1] = (int32_t)nt;
         act[s + 1] = act[s] + n;
-        koff[s + 1] = (int32_t)nk;
-        kgrp[s] = (int32_t)G;
     }
     RC(upload_desc(c, lv, nseg));
-    GridLevelArgs a{lv.seg, lv.offs, lv.offs + S1, lv.offs + 2 * S1, lv.offs + 3 * S1, lv.offs + 4 * S1,
-                    nseg, chunk[nseg], tile[nseg], act[nseg], koff[nseg], next_epoch(c)};
+    GridLevelArgs a{lv.seg, lv.offs, lv.offs + S1, lv.offs + 2 * S1, nseg, chunk[nseg], tile[nseg], act[nseg],
+                    next_epoch(c)};
     const bool exact = exact_order(c);
-    if (!exact && (size_t)a.nkblocks > c->kick_part_cap) {
-        RC(dalloc(c, &c->kick_part, (size_t)a.nkblocks * 3 * TPB));
-        c->kick_part_cap = a.nkblocks;
-    }
     {
         Span s(c, F_STAR);
         HIPCHK(launch_star(W, a, lv.notstar, c->parent, c->cnt, p, h, screen32(c), c->stats, fam_ptr(c, F_STAR),
@@ -608,15 +689,19 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
 
     if (!exact) {
         // Component-contiguous order throughout: (the first drift, queued
-        // above), first half, kick and closing drift of the level, second
-        // half, then back to the entry order.
+        // above), the kick list, first half, kick and closing drift of the
+        // level, second half, then back to the entry order.
+        int nblk = 0;
+        RC(upload_kick_list(c, lv, segs, big, &nblk));
+        const KickTile *ktile = reinterpret_cast<const KickTile *>(lv.kick);
+        const KickBlock *kblk = reinterpret_cast<const KickBlock *>(lv.kick + (size_t)a.nchunks * sizeof(KickTile));
         if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
         Level &lv2 = c->levels[k];
         {
             // the kick, then the second drift of the singletons (fused)
             Span s(c, F_KICK);
-            HIPCHK(launch_kick_tiles(W, a, lv2.labp, lv2.singp, h, c->params.eps2, c->params.G, mixed(c),
-                                     c->kick_part, c->errf, c->stats, fam_ptr(c, F_KICK), c->st));
+            HIPCHK(launch_kick_tiles(W, a, kblk, nblk, ktile, lv2.labp, lv2.singp, h, c->params.eps2, c->params.G,
+                                     mixed(c), c->kick_part, c->errf, c->stats, fam_ptr(c, F_KICK), c->st));
         }
         if (any_sub) {
             RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
@@ -954,8 +1039,9 @@ void cc_destroy(cc_ctx *c)
     for (auto &lv : c->levels) {
         F(lv.label); F(lv.sing); F(lv.labp); F(lv.singp); F(lv.src); F(lv.pairs);
         for (auto *p : lv.small) F(p);
-        F(lv.rep); F(lv.notstar); F(lv.desc);
-        FH(lv.h_rep); FH(lv.h_desc);
+        F(lv.rep); F(lv.notstar); F(lv.desc); F(lv.kick);
+        FH(lv.h_rep); FH(lv.h_desc); FH(lv.h_kick);
+        if (lv.kick_ev) hipEventDestroy(lv.kick_ev);
     }
     for (auto &r : c->recs) {
         hipEventDestroy(r.a);
@@ -1019,7 +1105,7 @@ int cc_split_labels(cc_ctx *c, const cc_state *s, int64_t n, double h, int32_t *
     int32_t *o = lv.h_offs;
     o[0] = 0; o[1] = T; o[2] = 0; o[3] = NT; o[4] = 0; o[5] = (int32_t)n;
     RC(upload_desc(c, lv, 1));
-    GridLevelArgs a{lv.seg, lv.offs, lv.offs + 2, lv.offs + 4, nullptr, nullptr, 1, T, NT, (int)n, 0, next_epoch(c)};
+    GridLevelArgs a{lv.seg, lv.offs, lv.offs + 2, lv.offs + 4, 1, T, NT, (int)n, next_epoch(c)};
     HIPCHK(hipMemsetAsync(c->stats, 0, ST_N * sizeof(uint64_t), c->st));
     const DevParams p = dev_params(c);
     SoA S = user_soa(s);

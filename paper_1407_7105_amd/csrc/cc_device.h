@@ -27,6 +27,20 @@ struct Seg {
     int32_t start, n, cluster, depth;
 };
 
+// One block of the tiled kick: i tile `itile` (256 slots) of segment `seg`
+// against partners [j0, j0 + nj) of the same segment (offsets within it).
+struct KickBlock {
+    int32_t seg, itile, j0, nj;
+};
+
+// The kick blocks of one i tile: [b0, b0 + nb) of the block list.
+struct KickTile {
+    int32_t b0, nb;
+};
+
+// Granularity of the kick's j ranges (partners per block are a multiple).
+constexpr int KICK_JW = 32;
+
 // Statistics slots (per cluster, uint64 each).
 enum StatIdx {
     ST_TAU = 0,       // pair time steps evaluated
@@ -327,6 +341,31 @@ __device__ __forceinline__ bool accel_term_rsq(double xi, double yi, double zi, 
     ay = __builtin_fma(f, dy, ay);
     az = __builtin_fma(f, dz, az);
     return r2 != 0.0;
+}
+
+// The same term behind a mask, for loops without a branch per partner: a
+// partner that is off (same component, or the particle itself) contributes a
+// zero factor whatever its distance, and raises no error.
+__device__ __forceinline__ bool accel_term_rsq_if(bool on, double xi, double yi, double zi, double xj, double yj,
+                                                  double zj, double gmj, double eps2, double &ax, double &ay,
+                                                  double &az)
+{
+    const double dx = xj - xi;
+    const double dy = yj - yi;
+    const double dz = zj - zi;
+    const double r2 = __builtin_fma(dx, dx, __builtin_fma(dy, dy, __builtin_fma(dz, dz, eps2)));
+    // an off partner sees r2 = 1 and mass 0: a finite zero factor
+    const double rs = on ? r2 : 1.0;
+    double y = __builtin_amdgcn_rsq(rs);
+    double e = __builtin_fma(-(rs * y), y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    e = __builtin_fma(-(rs * y), y, 1.0);
+    y = __builtin_fma(0.5 * y, e, y);
+    const double f = (on ? gmj : 0.0) * (y * (y * y));
+    ax = __builtin_fma(f, dx, ax);
+    ay = __builtin_fma(f, dy, ay);
+    az = __builtin_fma(f, dz, az);
+    return !on || r2 != 0.0;
 }
 
 // ---------------------------------------------------------------------------

@@ -612,17 +612,15 @@ __global__ __launch_bounds__(TPB) void k_kick_seg(SoA W, const Seg *__restrict__
 }
 
 // Kick K_h in the component-contiguous slot order (labels non-decreasing
-// within a segment).  Block b covers one 256-particle i tile and one group of
-// j tiles of its segment; a j tile lying inside the i tile's own component is
-// skipped whole (all its pairs are inside one component).  Each block writes
-// its partial accelerations; k_kick_combine adds the groups of every i in
-// group order, so the result is deterministic.
-constexpr int KICK_JW = 32;  // granularity of the j ranges of the kick groups
-
+// within a segment).  Block b takes the i tile and j range of blk[b]; the
+// host leaves out of the ranges of an i tile that lies inside one large
+// component that component itself (all of its pairs are inside it), and a j
+// tile inside the i tile's own component is skipped whole here.  Each block
+// writes its partial accelerations; k_kick_combine adds the blocks of every i
+// tile in list order, so the result is deterministic.
 template <bool MIXED>
 __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict__ seg,
-                                                     const int32_t *__restrict__ kick_off,
-                                                     const int32_t *__restrict__ kgrp, int nseg,
+                                                     const KickBlock *__restrict__ blk,
                                                      const int32_t *__restrict__ labp, double eps2, double G,
                                                      double *__restrict__ part, int32_t *err, uint64_t *stats,
                                                      uint64_t *fam)
@@ -630,14 +628,10 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
     __shared__ double jx[TPB], jy[TPB], jz[TPB], jm[TPB];
     __shared__ int32_t jl[TPB];
     __shared__ uint64_t sh[4];
-    const int s = find_seg(kick_off, nseg, blockIdx.x);
-    const Seg g = seg[s];
-    const int Gs = kgrp[s];
-    const int local = blockIdx.x - kick_off[s];
-    const int I = local / Gs, grp = local % Gs;
-    // j range of this group: Gs equal ranges, multiples of KICK_JW partners
-    const int jw = (((g.n + Gs - 1) / Gs) + KICK_JW - 1) / KICK_JW * KICK_JW;
-    const int jlo = min(g.n, grp * jw), jhi = min(g.n, jlo + jw);
+    const KickBlock kb = blk[blockIdx.x];
+    const Seg g = seg[kb.seg];
+    const int I = kb.itile;
+    const int jlo = kb.j0, jhi = kb.j0 + kb.nj;
     const int il = I * TPB + threadIdx.x;
     const bool valid = il < g.n;
     const int i = g.start + (valid ? il : 0);
@@ -677,11 +671,16 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
                 ay += (double)k.sy - (double)k.cy;
                 az += (double)k.sz - (double)k.cz;
             } else {
+                // no branch per partner: partners of the own component add
+                // a zero factor
+                uint32_t np = 0;
+#pragma unroll 2
                 for (int jj = 0; jj < jn; ++jj) {
-                    if (jl[jj] == li) continue;
-                    ok &= accel_term_rsq(xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, ax, ay, az);
-                    pairs += (jb + jj > il);
+                    const bool on = jl[jj] != li;
+                    ok &= accel_term_rsq_if(on, xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, ax, ay, az);
+                    np += (on && jb + jj > il) ? 1u : 0u;
                 }
+                pairs += np;
             }
         }
     }
@@ -697,12 +696,11 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
     }
 }
 
-// Adds the partial accelerations of every i in group order, applies the kick,
-// then the drift D_{hh} of the singletons that ends the level's D K D.
+// Adds the partial accelerations of every i in block-list order, applies the
+// kick, then the drift D_{hh} of the singletons that ends the level's D K D.
 __global__ __launch_bounds__(TPB) void k_kick_combine(SoA W, const Seg *__restrict__ seg,
                                                        const int32_t *__restrict__ chunk_off,
-                                                       const int32_t *__restrict__ kick_off,
-                                                       const int32_t *__restrict__ kgrp, int nseg,
+                                                       const KickTile *__restrict__ ktile, int nseg,
                                                        const double *__restrict__ part, double h,
                                                        const uint8_t *__restrict__ sing, double hh,
                                                        uint64_t *stats)
@@ -714,10 +712,12 @@ __global__ __launch_bounds__(TPB) void k_kick_combine(SoA W, const Seg *__restri
     const int il = I * TPB + threadIdx.x;
     uint64_t drifted = 0;
     if (il < g.n) {
-        const int Gs = kgrp[s];
-        const double *pb = part + (size_t)(kick_off[s] + I * Gs) * 3 * TPB;
+        const KickTile kt = ktile[blockIdx.x];
+        const double *pb = part + (size_t)kt.b0 * 3 * TPB;
         double ax = 0.0, ay = 0.0, az = 0.0;
-        for (int q = 0; q < Gs; ++q) {
+        // in order; unrolled so that many partial loads are in flight
+#pragma unroll 8
+        for (int q = 0; q < kt.nb; ++q) {
             ax += pb[(size_t)q * 3 * TPB + threadIdx.x];
             ay += pb[(size_t)q * 3 * TPB + TPB + threadIdx.x];
             az += pb[(size_t)q * 3 * TPB + 2 * TPB + threadIdx.x];
@@ -1662,18 +1662,20 @@ hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, 
     return hipGetLastError();
 }
 
-hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const int32_t *labp, const uint8_t *singp, double h,
-                             double eps2, double G, bool mixed, double *part, int32_t *err, uint64_t *stats,
-                             uint64_t *fam, hipStream_t st)
+hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk, int nblk, const KickTile *ktile,
+                             const int32_t *labp, const uint8_t *singp, double h, double eps2, double G, bool mixed,
+                             double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
-    if (mixed)
-        hipLaunchKernelGGL(k_kick_tiles<true>, dim3(a.nkblocks), dim3(TPB), 0, st, W, a.seg, a.kick_off, a.kgrp,
-                           a.nseg, labp, eps2, G, part, err, stats, fam);
-    else
-        hipLaunchKernelGGL(k_kick_tiles<false>, dim3(a.nkblocks), dim3(TPB), 0, st, W, a.seg, a.kick_off, a.kgrp,
-                           a.nseg, labp, eps2, G, part, err, stats, fam);
-    hipLaunchKernelGGL(k_kick_combine, dim3(a.nchunks), dim3(TPB), 0, st, W, a.seg, a.chunk_off, a.kick_off, a.kgrp,
-                       a.nseg, (const double *)part, h, singp, 0.5 * h, stats);
+    if (nblk > 0) {
+        if (mixed)
+            hipLaunchKernelGGL(k_kick_tiles<true>, dim3(nblk), dim3(TPB), 0, st, W, a.seg, blk, labp, eps2, G, part,
+                               err, stats, fam);
+        else
+            hipLaunchKernelGGL(k_kick_tiles<false>, dim3(nblk), dim3(TPB), 0, st, W, a.seg, blk, labp, eps2, G, part,
+                               err, stats, fam);
+    }
+    hipLaunchKernelGGL(k_kick_combine, dim3(a.nchunks), dim3(TPB), 0, st, W, a.seg, a.chunk_off, ktile, a.nseg,
+                       (const double *)part, h, singp, 0.5 * h, stats);
     return hipGetLastError();
 }
 

@@ -15,9 +15,7 @@ struct GridLevelArgs {
     const int32_t *chunk_off;  // prefix over ceil(n/256) slot chunks, nseg+1
     const int32_t *tile_off;   // prefix over triangular 256x256 tiles (non-star sweep), nseg+1
     const int32_t *act_off;    // prefix over n, nseg+1
-    const int32_t *kick_off;   // prefix over kick blocks (i tiles x j groups), nseg+1
-    const int32_t *kgrp;       // j groups per segment, nseg
-    int nseg, nchunks, ntiles, nact, nkblocks;
+    int nseg, nchunks, ntiles, nact;
     int32_t epoch;             // marks this visit's non-star flags (no clearing between visits)
 };
 
@@ -80,9 +78,11 @@ hipError_t launch_drift_seg(SoA W, const GridLevelArgs &a, const uint8_t *sing, 
 hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, double h, double eps2, double G,
                            int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
 // kick K_h of the level, then the drift D_{h/2} of its singletons (singp)
-hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const int32_t *labp, const uint8_t *singp, double h,
-                             double eps2, double G, bool mixed, double *part, int32_t *err, uint64_t *stats,
-                             uint64_t *fam, hipStream_t st);
+// Tiled kick of a level (blocks listed by the host, see KickBlock) and the
+// combine that applies it with the singletons' closing drift.
+hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk, int nblk, const KickTile *ktile,
+                             const int32_t *labp, const uint8_t *singp, double h, double eps2, double G, bool mixed,
+                             double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
 hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, double *ax, double *ay,
                            double *az, int32_t *err, hipStream_t st);
 hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, const double *az, double h,
