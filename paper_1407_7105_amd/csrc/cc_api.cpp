@@ -69,7 +69,7 @@ struct Level {
     Seg *seg = nullptr, *h_seg = nullptr;
     int32_t *offs = nullptr, *h_offs = nullptr;
     // Kick list, uploaded once the level's components are known: one
-    // KickTile per i tile followed by the KickBlocks.  kick_ev marks the end
+    // KickTile per i tile, the KickBlocks, the KickJobs.  kick_ev marks the end
     // of the last upload from h_kick, which the next visit must not overwrite
     // before.
     unsigned char *kick = nullptr, *h_kick = nullptr;
@@ -470,8 +470,11 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h);
 // chosen so that the launch has about kick_groups blocks per compute unit of
 // equal work, wherever in the segments the work lies.  The list (a KickTile
 // per i tile, then the blocks) goes up with one copy on the main stream, and
-// the partial-acceleration buffer grows to the block count.
-int upload_kick_list(cc_ctx *c, Level &lv, const std::vector<Seg> &segs, const std::vector<Seg> &big, int *nblk_out)
+// the partial-acceleration buffer grows to the slot count.  A tile with more
+// than KICK_FANIN blocks is summed in two stages: group sums of KICK_FANIN
+// consecutive blocks (KickJobs, slots after the blocks'), then the groups.
+int upload_kick_list(cc_ctx *c, Level &lv, const std::vector<Seg> &segs, const std::vector<Seg> &big, int *nblk_out,
+                     int *njobs_out)
 {
     // per i tile, the partners [xlo, xhi) it leaves out (offsets within the
     // segment; empty when xlo == xhi)
@@ -504,14 +507,24 @@ int upload_kick_list(cc_ctx *c, Level &lv, const std::vector<Seg> &segs, const s
         for (const Seg &g : segs)
             for (int I = 0; I < (g.n + TPB - 1) / TPB; ++I, ++t) nblk += nchunk(tr[2 * t]) + nchunk(g.n - tr[2 * t + 1]);
     }
-    if (nblk > INT32_MAX) return fail(c, CC_ERR_ARG, "kick list too long");
     const size_t ntile = tr.size() / 2;
-    const size_t bytes = ntile * sizeof(KickTile) + (size_t)nblk * sizeof(KickBlock);
+    int64_t njobs = 0;
+    {
+        size_t t = 0;
+        for (const Seg &g : segs)
+            for (int I = 0; I < (g.n + TPB - 1) / TPB; ++I, ++t) {
+                const int64_t nb = nchunk(tr[2 * t]) + nchunk(g.n - tr[2 * t + 1]);
+                if (nb > KICK_FANIN) njobs += (nb + KICK_FANIN - 1) / KICK_FANIN;
+            }
+    }
+    if (nblk + njobs > INT32_MAX) return fail(c, CC_ERR_ARG, "kick list too long");
+    const size_t nslot = (size_t)(nblk + njobs);
+    const size_t bytes = ntile * sizeof(KickTile) + (size_t)nblk * sizeof(KickBlock) + (size_t)njobs * sizeof(KickJob);
     if (lv.kick_pending) {
         HIPCHK(hipEventSynchronize(lv.kick_ev));
         lv.kick_pending = false;
     }
-    if (bytes > lv.cap_kick || (size_t)nblk > c->kick_part_cap) {
+    if (bytes > lv.cap_kick || nslot > c->kick_part_cap) {
         // buffers still read by queued kicks: let both streams drain first
         HIPCHK(hipStreamSynchronize(c->st));
         HIPCHK(hipStreamSynchronize(c->side));
@@ -521,8 +534,8 @@ int upload_kick_list(cc_ctx *c, Level &lv, const std::vector<Seg> &segs, const s
             RC(halloc(c, &lv.h_kick, cap));
             lv.cap_kick = cap;
         }
-        if ((size_t)nblk > c->kick_part_cap) {
-            const size_t cap = std::max((size_t)nblk, 2 * c->kick_part_cap);
+        if (nslot > c->kick_part_cap) {
+            const size_t cap = std::max(nslot, 2 * c->kick_part_cap);
             RC(dalloc(c, &c->kick_part, cap * 3 * TPB));
             c->kick_part_cap = cap;
         }
@@ -530,23 +543,35 @@ int upload_kick_list(cc_ctx *c, Level &lv, const std::vector<Seg> &segs, const s
     if (!lv.kick_ev) HIPCHK(hipEventCreateWithFlags(&lv.kick_ev, hipEventDisableTiming));
     KickTile *kt = reinterpret_cast<KickTile *>(lv.h_kick);
     KickBlock *kb = reinterpret_cast<KickBlock *>(lv.h_kick + ntile * sizeof(KickTile));
-    int32_t b = 0;
+    KickJob *kj = reinterpret_cast<KickJob *>(lv.h_kick + ntile * sizeof(KickTile) + (size_t)nblk * sizeof(KickBlock));
+    int32_t b = 0, j = 0;
     size_t t = 0;
     for (int s = 0; s < (int)segs.size(); ++s) {
         const Seg &g = segs[s];
         for (int I = 0; I < (g.n + TPB - 1) / TPB; ++I, ++t) {
-            kt[t].b0 = b;
+            const int32_t b0 = b;
             const int32_t ranges[2][2] = {{0, tr[2 * t]}, {tr[2 * t + 1], g.n}};
             for (const auto &r : ranges)
                 for (int64_t j0 = r[0]; j0 < r[1]; j0 += cj)
                     kb[b++] = KickBlock{s, I, (int32_t)j0, (int32_t)std::min<int64_t>(cj, r[1] - j0)};
-            kt[t].nb = b - kt[t].b0;
+            const int32_t nb = b - b0;
+            if (nb <= KICK_FANIN) {
+                kt[t] = KickTile{b0, nb};
+            } else {
+                const int32_t g0 = (int32_t)nblk + j;
+                for (int32_t q = 0; q < nb; q += KICK_FANIN) {
+                    kj[j] = KickJob{b0 + q, std::min<int32_t>(KICK_FANIN, nb - q), (int32_t)nblk + j, 0};
+                    ++j;
+                }
+                kt[t] = KickTile{g0, (int32_t)nblk + j - g0};
+            }
         }
     }
     HIPCHK(hipMemcpyAsync(lv.kick, lv.h_kick, bytes, hipMemcpyHostToDevice, c->st));
     HIPCHK(hipEventRecord(lv.kick_ev, c->st));
     lv.kick_pending = true;
     *nblk_out = (int)nblk;
+    *njobs_out = (int)njobs;
     return CC_OK;
 }
 
@@ -691,17 +716,20 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         // Component-contiguous order throughout: (the first drift, queued
         // above), the kick list, first half, kick and closing drift of the
         // level, second half, then back to the entry order.
-        int nblk = 0;
-        RC(upload_kick_list(c, lv, segs, big, &nblk));
+        int nblk = 0, njobs = 0;
+        RC(upload_kick_list(c, lv, segs, big, &nblk, &njobs));
         const KickTile *ktile = reinterpret_cast<const KickTile *>(lv.kick);
         const KickBlock *kblk = reinterpret_cast<const KickBlock *>(lv.kick + (size_t)a.nchunks * sizeof(KickTile));
+        const KickJob *kjob = reinterpret_cast<const KickJob *>(lv.kick + (size_t)a.nchunks * sizeof(KickTile) +
+                                                                (size_t)nblk * sizeof(KickBlock));
         if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
         Level &lv2 = c->levels[k];
         {
             // the kick, then the second drift of the singletons (fused)
             Span s(c, F_KICK);
-            HIPCHK(launch_kick_tiles(W, a, kblk, nblk, ktile, lv2.labp, lv2.singp, h, c->params.eps2, c->params.G,
-                                     mixed(c), c->kick_part, c->errf, c->stats, fam_ptr(c, F_KICK), c->st));
+            HIPCHK(launch_kick_tiles(W, a, kblk, nblk, kjob, njobs, ktile, lv2.labp, lv2.singp, h, c->params.eps2,
+                                     c->params.G, mixed(c), c->kick_part, c->errf, c->stats, fam_ptr(c, F_KICK),
+                                     c->st));
         }
         if (any_sub) {
             RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));

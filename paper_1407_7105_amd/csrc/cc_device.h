@@ -33,10 +33,20 @@ struct KickBlock {
     int32_t seg, itile, j0, nj;
 };
 
-// The kick blocks of one i tile: [b0, b0 + nb) of the block list.
+// The partial accelerations of the kick live in slots of 3 x 256 doubles:
+// first one slot per kick block, then one per group sum.  An i tile's kick
+// is the in-order sum of slots [src, src + n).
 struct KickTile {
-    int32_t b0, nb;
+    int32_t src, n;
 };
+
+// A group sum: slots [src, src + n) added in order into slot dst (n is at
+// most KICK_FANIN).  Tiles with more kick blocks than that are reduced in
+// two stages, so that no sum runs long.
+struct KickJob {
+    int32_t src, n, dst, pad;
+};
+constexpr int KICK_FANIN = 16;
 
 // Granularity of the kick's j ranges (partners per block are a multiple).
 constexpr int KICK_JW = 32;

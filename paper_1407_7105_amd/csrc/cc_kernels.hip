@@ -696,8 +696,26 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
     }
 }
 
-// Adds the partial accelerations of every i in block-list order, applies the
-// kick, then the drift D_{hh} of the singletons that ends the level's D K D.
+// Group sums of the two-stage reduction: job b adds its slots in order.
+__global__ __launch_bounds__(TPB) void k_kick_reduce(const KickJob *__restrict__ jobs, double *__restrict__ part)
+{
+    const KickJob jb = jobs[blockIdx.x];
+    const double *pb = part + (size_t)jb.src * 3 * TPB;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < jb.n; ++q) {
+        ax += pb[(size_t)q * 3 * TPB + threadIdx.x];
+        ay += pb[(size_t)q * 3 * TPB + TPB + threadIdx.x];
+        az += pb[(size_t)q * 3 * TPB + 2 * TPB + threadIdx.x];
+    }
+    double *po = part + (size_t)jb.dst * 3 * TPB;
+    po[threadIdx.x] = ax;
+    po[TPB + threadIdx.x] = ay;
+    po[2 * TPB + threadIdx.x] = az;
+}
+
+// Adds the partial accelerations of every i in slot order, applies the kick,
+// then the drift D_{hh} of the singletons that ends the level's D K D.
 __global__ __launch_bounds__(TPB) void k_kick_combine(SoA W, const Seg *__restrict__ seg,
                                                        const int32_t *__restrict__ chunk_off,
                                                        const KickTile *__restrict__ ktile, int nseg,
@@ -713,11 +731,11 @@ __global__ __launch_bounds__(TPB) void k_kick_combine(SoA W, const Seg *__restri
     uint64_t drifted = 0;
     if (il < g.n) {
         const KickTile kt = ktile[blockIdx.x];
-        const double *pb = part + (size_t)kt.b0 * 3 * TPB;
+        const double *pb = part + (size_t)kt.src * 3 * TPB;
         double ax = 0.0, ay = 0.0, az = 0.0;
         // in order; unrolled so that many partial loads are in flight
 #pragma unroll 8
-        for (int q = 0; q < kt.nb; ++q) {
+        for (int q = 0; q < kt.n; ++q) {
             ax += pb[(size_t)q * 3 * TPB + threadIdx.x];
             ay += pb[(size_t)q * 3 * TPB + TPB + threadIdx.x];
             az += pb[(size_t)q * 3 * TPB + 2 * TPB + threadIdx.x];
@@ -1662,9 +1680,10 @@ hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, 
     return hipGetLastError();
 }
 
-hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk, int nblk, const KickTile *ktile,
-                             const int32_t *labp, const uint8_t *singp, double h, double eps2, double G, bool mixed,
-                             double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
+hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk, int nblk, const KickJob *jobs,
+                             int njobs, const KickTile *ktile, const int32_t *labp, const uint8_t *singp, double h,
+                             double eps2, double G, bool mixed, double *part, int32_t *err, uint64_t *stats,
+                             uint64_t *fam, hipStream_t st)
 {
     if (nblk > 0) {
         if (mixed)
@@ -1674,6 +1693,7 @@ hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk
             hipLaunchKernelGGL(k_kick_tiles<false>, dim3(nblk), dim3(TPB), 0, st, W, a.seg, blk, labp, eps2, G, part,
                                err, stats, fam);
     }
+    if (njobs > 0) hipLaunchKernelGGL(k_kick_reduce, dim3(njobs), dim3(TPB), 0, st, jobs, part);
     hipLaunchKernelGGL(k_kick_combine, dim3(a.nchunks), dim3(TPB), 0, st, W, a.seg, a.chunk_off, ktile, a.nseg,
                        (const double *)part, h, singp, 0.5 * h, stats);
     return hipGetLastError();

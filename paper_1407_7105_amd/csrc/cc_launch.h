@@ -78,11 +78,13 @@ hipError_t launch_drift_seg(SoA W, const GridLevelArgs &a, const uint8_t *sing, 
 hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, double h, double eps2, double G,
                            int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
 // kick K_h of the level, then the drift D_{h/2} of its singletons (singp)
-// Tiled kick of a level (blocks listed by the host, see KickBlock) and the
-// combine that applies it with the singletons' closing drift.
-hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk, int nblk, const KickTile *ktile,
-                             const int32_t *labp, const uint8_t *singp, double h, double eps2, double G, bool mixed,
-                             double *part, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
+// Tiled kick of a level (blocks listed by the host, see KickBlock), the group
+// sums (KickJob) and the combine that applies the kick with the singletons'
+// closing drift.
+hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk, int nblk, const KickJob *jobs,
+                             int njobs, const KickTile *ktile, const int32_t *labp, const uint8_t *singp, double h,
+                             double eps2, double G, bool mixed, double *part, int32_t *err, uint64_t *stats,
+                             uint64_t *fam, hipStream_t st);
 hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, double *ax, double *ay,
                            double *az, int32_t *err, hipStream_t st);
 hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, const double *az, double h,
