@@ -102,7 +102,7 @@ struct cc_ctx {
     int32_t *orig = nullptr;
     double *snap[6] = {};
     double *tmp[7] = {};
-    int32_t *tmp_orig = nullptr, *tmp_lab = nullptr;
+    int32_t *tmp_orig = nullptr;
     uint32_t *keys = nullptr, *keys_out = nullptr, *vals = nullptr;
     void *sort_temp = nullptr;
     size_t sort_bytes = 0;
@@ -229,7 +229,6 @@ int ensure_capacity(cc_ctx *c, size_t n, size_t ncl)
         for (int a = 0; a < 7; ++a) RC(dalloc(c, &c->tmp[a], cap));
         RC(dalloc(c, &c->orig, cap));
         RC(dalloc(c, &c->tmp_orig, cap));
-        RC(dalloc(c, &c->tmp_lab, cap));
         RC(dalloc(c, &c->keys, cap));
         RC(dalloc(c, &c->keys_out, cap));
         RC(dalloc(c, &c->vals, cap));
@@ -296,8 +295,13 @@ int ensure_level(cc_ctx *c, int k, size_t nseg)
     return CC_OK;
 }
 
-SoA work_soa(cc_ctx *c)
+// The two working buffers: a level at grid depth k holds its sets in buffer
+// k % 2 and makes their components contiguous in the other one (each
+// permutation is one out-of-place launch).  Buffer 0 holds the state between
+// steps.
+SoA work_soa(cc_ctx *c, int parity)
 {
+    if (parity & 1) return SoA{c->tmp[0], c->tmp[1], c->tmp[2], c->tmp[3], c->tmp[4], c->tmp[5], c->tmp[6], c->tmp_orig};
     return SoA{c->w[0], c->w[1], c->w[2], c->w[3], c->w[4], c->w[5], c->w[6], c->orig};
 }
 
@@ -435,14 +439,15 @@ int upload_desc(cc_ctx *c, Level &lv, int nseg)
 // A level's two-particle and small components in one launch.  Queue
 // counters are per level: the launch of a level may still run on the side
 // stream while a deeper level launches its own.  n_small[b] = items in size
-// bin b.
-int run_small_and_pairs(cc_ctx *c, int k, Level &lv, double H, int n_pairs, const int n_small[4], hipStream_t st)
+// bin b; the items live in working buffer `parity`.
+int run_small_and_pairs(cc_ctx *c, int k, Level &lv, double H, int n_pairs, const int n_small[4], hipStream_t st,
+                        int parity)
 {
     const int n_block_items = n_small[2] + n_small[3];
     const int n_wave_items = n_small[0] + n_small[1];
     if (n_pairs + n_block_items + n_wave_items == 0) return CC_OK;
     const DevParams p = dev_params(c);
-    SoA W = work_soa(c);
+    SoA W = work_soa(c, parity);
     SmallArgs sa{};
     sa.pairs = lv.pairs;
     for (int b = 0; b < 4; ++b) sa.bin[b] = lv.small[b];
@@ -585,12 +590,12 @@ int dispatch_sets(cc_ctx *c, int k, Level &lv, double H, const std::vector<Seg> 
 {
     const bool on_chip = n_pairs + n_small[0] + n_small[1] + n_small[2] + n_small[3] > 0;
     if (!on_chip || big.empty()) {
-        RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, c->st));
+        RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, c->st, k + 1));
         if (!big.empty()) RC(evolve_grid(c, k + 1, big, H));
         return CC_OK;
     }
     RC(order_streams(c, c->st, c->side));
-    RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, c->side));
+    RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, c->side, k + 1));
     hipEvent_t done;
     RC(take_event(c, &done));
     HIPCHK(hipEventRecord(done, c->side));
@@ -617,7 +622,8 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     RC(ensure_level(c, k, nseg));
     Level &lv = c->levels[k];
     const DevParams p = dev_params(c);
-    SoA W = work_soa(c);
+    SoA W = work_soa(c, k);       // the sets of this level, entry order
+    SoA Wp = work_soa(c, k + 1);  // the same slots, component-contiguous
 
     // segment descriptors and prefix arrays
     const size_t S1 = (size_t)nseg + 1;
@@ -663,7 +669,6 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         Span s(c, F_SORT);
         HIPCHK(launch_sort(c->sort_temp, c->sort_bytes, c->keys, c->keys_out, c->vals, lv.src, a.nact, end_bit, c->st));
     }
-    TmpArrays T{c->tmp[0], c->tmp[1], c->tmp[2], c->tmp[3], c->tmp[4], c->tmp[5], c->tmp[6], c->tmp_orig, c->tmp_lab};
     ListArgs L{};
     L.pairs = lv.pairs;
     for (int b = 0; b < 4; ++b) L.small[b] = lv.small[b];
@@ -681,14 +686,14 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     L.errf = c->errf;
     {
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(W, T, a, lv.src, lv.label, c->cnt, lv.sing, &L, c->stats, false, c->st));
+        HIPCHK(launch_permute(W, Wp, a, lv.src, c->keys_out, c->cnt, lv.sing, &L, c->stats, false, c->st));
     }
     if (!exact) {
         // The singletons' first drift touches no particle of a component, so
         // it may precede the first-half recursion: queued before the host
         // waits for the report, it runs while the host reads it.
         Span s(c, F_DRIFT);
-        HIPCHK(launch_drift_seg(W, a, lv.singp, 0.5 * h, c->stats, c->st));
+        HIPCHK(launch_drift_seg(Wp, a, lv.singp, 0.5 * h, c->stats, c->st));
     }
     HIPCHK(hipMemcpyAsync(lv.h_rep, lv.rep, 8 * sizeof(int32_t) + (size_t)lv.cap_big * sizeof(Seg),
                           hipMemcpyDeviceToHost, c->st));
@@ -727,26 +732,24 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         {
             // the kick, then the second drift of the singletons (fused)
             Span s(c, F_KICK);
-            HIPCHK(launch_kick_tiles(W, a, kblk, nblk, kjob, njobs, ktile, lv2.labp, lv2.singp, h, c->params.eps2,
+            HIPCHK(launch_kick_tiles(Wp, a, kblk, nblk, kjob, njobs, ktile, lv2.labp, lv2.singp, h, c->params.eps2,
                                      c->params.G, mixed(c), c->kick_part, c->errf, c->stats, fam_ptr(c, F_KICK),
                                      c->st));
         }
-        if (any_sub) {
-            RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
-            Level &lv3 = c->levels[k];
-            Span s(c, F_PERMUTE);
-            HIPCHK(launch_permute(W, T, a, lv3.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
-        }
+        if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
+        Level &lv3 = c->levels[k];
+        Span s(c, F_PERMUTE);
+        HIPCHK(launch_permute(Wp, W, a, lv3.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
         return CC_OK;
     }
 
     // Exact order: the level's drift/kick/drift runs in the entry order, in
     // which every set is ascending in particle index.
-    if (any_sub) {
-        RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
+    if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
+    {
         Level &lv2 = c->levels[k];
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(W, T, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
+        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
     }
     {
         Level &lv2 = c->levels[k];
@@ -769,12 +772,12 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         {
             Level &lv2 = c->levels[k];
             Span s(c, F_PERMUTE);
-            HIPCHK(launch_permute(W, T, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, false, c->st));
+            HIPCHK(launch_permute(W, Wp, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, false, c->st));
         }
         RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
         Level &lv2 = c->levels[k];
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(W, T, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
+        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
     }
     return CC_OK;
 }
@@ -821,7 +824,7 @@ int global_step(cc_ctx *c, const std::vector<Seg> &top, double dt)
     int n_pairs = 0, n_small[4] = {0, 0, 0, 0};
     RC(route_top(c, top, big, n_pairs, n_small));
     if (n_pairs + n_small[0] + n_small[1] + n_small[2] + n_small[3] > 0)
-        RC(run_small_and_pairs(c, 0, c->levels[0], dt, n_pairs, n_small, c->st));
+        RC(run_small_and_pairs(c, 0, c->levels[0], dt, n_pairs, n_small, c->st, 0));
     if (!big.empty()) RC(evolve_grid(c, 0, big, dt));
     return CC_OK;
 }
@@ -856,7 +859,7 @@ int evolve_on_chip_graph(cc_ctx *c, const std::vector<Seg> &top, int64_t n, int6
         for (int a = 0; a < 6 && rc == CC_OK; ++a)
             if (hipMemcpyAsync(c->snap[a], c->w[a], bytes, hipMemcpyDeviceToDevice, g) != hipSuccess)
                 rc = fail(c, CC_ERR_DEVICE, "graph capture of the snapshot failed");
-        if (rc == CC_OK) rc = run_small_and_pairs(c, 0, c->levels[0], dt, n_pairs, n_small, g);
+        if (rc == CC_OK) rc = run_small_and_pairs(c, 0, c->levels[0], dt, n_pairs, n_small, g, 0);
         if (rc == CC_OK &&
             (launch_validate(c->w[0], c->w[1], c->w[2], c->w[3], c->w[4], c->w[5], c->w[6], n, c->errf, g) !=
                  hipSuccess ||
@@ -1060,7 +1063,7 @@ void cc_destroy(cc_ctx *c)
     for (auto *p : c->w) F(p);
     for (auto *p : c->snap) F(p);
     for (auto *p : c->tmp) F(p);
-    F(c->orig); F(c->tmp_orig); F(c->tmp_lab); F(c->keys); F(c->keys_out); F(c->vals); F(c->sort_temp);
+    F(c->orig); F(c->tmp_orig); F(c->keys); F(c->keys_out); F(c->vals); F(c->sort_temp);
     F(c->parent); F(c->cnt); F(c->stats); F(c->errf); F(c->qhead); F(c->kick_acc); F(c->kick_part); F(c->diag_part);
     F(c->diag_out); F(c->fam_work);
     FH(c->h_stats); FH(c->h_err); FH(c->h_diag);

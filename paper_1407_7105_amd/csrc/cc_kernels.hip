@@ -432,44 +432,7 @@ __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, cons
     }
 }
 
-struct Tmp {
-    double *x, *y, *z, *vx, *vy, *vz, *m;
-    int32_t *orig, *lab;
-};
-
-// T[k] = W[from[k]] (from == NULL: from = act(k)); optionally the entry
-// label of the moved particle and the entry-order singleton flag.
-__global__ void k_gather(SoA W, Tmp T, const Seg *__restrict__ seg, const int32_t *__restrict__ act_off,
-                         int nseg, int nact, const uint32_t *__restrict__ from, const int32_t *__restrict__ label,
-                         const int32_t *__restrict__ cnt, uint8_t *__restrict__ sing)
-{
-    const int k = blockIdx.x * TPB + threadIdx.x;
-    if (k >= nact) return;
-    int src;
-    if (from) {
-        src = (int)from[k];
-    } else {
-        const int s = find_seg(act_off, nseg, k);
-        src = seg[s].start + (k - act_off[s]);
-    }
-    T.x[k] = W.x[src];
-    T.y[k] = W.y[src];
-    T.z[k] = W.z[src];
-    T.vx[k] = W.vx[src];
-    T.vy[k] = W.vy[src];
-    T.vz[k] = W.vz[src];
-    T.m[k] = W.m[src];
-    T.orig[k] = W.orig[src];
-    if (label) {
-        const int32_t l = label[src];
-        T.lab[k] = l;
-        sing[src] = (cnt[l] == 1) ? 1 : 0;
-    }
-}
-
-// W[to[k]] = T[k] (to == NULL: to = act(k)).  With `lists`, also classify the
-// components now contiguous in slot order: pairs, small (binned by size) and
-// big components are appended to the level's work lists.
+// Work lists of a level, filled while its components are made contiguous.
 struct Lists {
     Seg *pairs;
     Seg *small[4];
@@ -483,36 +446,41 @@ struct Lists {
     const int32_t *errf; // error bits, copied to count[7] for the host's one read-back
 };
 
-__global__ void k_scatter(SoA W, Tmp T, const Seg *__restrict__ seg, const int32_t *__restrict__ act_off,
-                          int nseg, int nact, const uint32_t *__restrict__ to, const int32_t *__restrict__ cnt,
-                          Lists L, int with_lists, uint64_t *stats)
+// Forward permutation of a level between the two working buffers: the k-th
+// active particle in (label, slot) order, from slot src[k] of `from`, goes to
+// its segment's k-th slot of `to`, so that every component is contiguous.
+// With `lab` (the sorted labels) it also records the singleton flags in entry
+// order, and with the lists the component-contiguous labels and singleton
+// flags and the level's work lists (pairs, small components by size, big
+// components).  Reads and writes touch different buffers: one launch.
+__global__ void k_permute(SoA from, SoA to, const Seg *__restrict__ seg, const int32_t *__restrict__ act_off,
+                          int nseg, int nact, const uint32_t *__restrict__ src, const uint32_t *__restrict__ lab,
+                          const int32_t *__restrict__ cnt, uint8_t *__restrict__ sing, Lists L, int with_lists,
+                          uint64_t *stats)
 {
     const int k = blockIdx.x * TPB + threadIdx.x;
     if (k >= nact) return;
-    int dst;
-    int s = 0;
-    if (to) {
-        dst = (int)to[k];
-    } else {
-        s = find_seg(act_off, nseg, k);
-        dst = seg[s].start + (k - act_off[s]);
-    }
-    W.x[dst] = T.x[k];
-    W.y[dst] = T.y[k];
-    W.z[dst] = T.z[k];
-    W.vx[dst] = T.vx[k];
-    W.vy[dst] = T.vy[k];
-    W.vz[dst] = T.vz[k];
-    W.m[dst] = T.m[k];
-    W.orig[dst] = T.orig[k];
+    const int s = find_seg(act_off, nseg, k);
+    const int dst = seg[s].start + (k - act_off[s]);
+    const int u = (int)src[k];
+    to.x[dst] = from.x[u];
+    to.y[dst] = from.y[u];
+    to.z[dst] = from.z[u];
+    to.vx[dst] = from.vx[u];
+    to.vy[dst] = from.vy[u];
+    to.vz[dst] = from.vz[u];
+    to.m[dst] = from.m[u];
+    to.orig[dst] = from.orig[u];
+    if (!lab) return;
+    const int32_t l = (int32_t)lab[k];
+    if (sing) sing[u] = (cnt[l] == 1) ? 1 : 0;
     if (!with_lists) return;
     if (k == 0) L.count[7] = __hip_atomic_load(L.errf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int32_t l = T.lab[k];
     if (L.labp) {
         L.labp[dst] = l;
         L.singp[dst] = (cnt[l] == 1) ? 1 : 0;
     }
-    const bool first = (k == act_off[s]) || (T.lab[k - 1] != l);
+    const bool first = (k == act_off[s]) || ((int32_t)lab[k - 1] != l);
     if (!first) return;
     const int32_t size = cnt[l];
     if (size < 2) return;
@@ -530,6 +498,26 @@ __global__ void k_scatter(SoA W, Tmp T, const Seg *__restrict__ seg, const int32
         const int i = atomicAdd(&L.count[5], 1);
         if (i < L.cap_big) L.big[i] = c;
     }
+}
+
+// Inverse permutation: the k-th slot of its segment in `from` goes back to
+// slot src[k] of `to` (entry order).
+__global__ void k_unpermute(SoA from, SoA to, const Seg *__restrict__ seg, const int32_t *__restrict__ act_off,
+                            int nseg, int nact, const uint32_t *__restrict__ src)
+{
+    const int k = blockIdx.x * TPB + threadIdx.x;
+    if (k >= nact) return;
+    const int s = find_seg(act_off, nseg, k);
+    const int v = seg[s].start + (k - act_off[s]);
+    const int u = (int)src[k];
+    to.x[u] = from.x[v];
+    to.y[u] = from.y[v];
+    to.z[u] = from.z[v];
+    to.vx[u] = from.vx[v];
+    to.vy[u] = from.vy[v];
+    to.vz[u] = from.vz[v];
+    to.m[u] = from.m[v];
+    to.orig[u] = from.orig[v];
 }
 
 // Drift D_{hh} of the segment's singletons (entry order).
@@ -1625,42 +1613,34 @@ hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, u
                                      false);
 }
 
-hipError_t launch_permute(SoA W, const TmpArrays &t, const GridLevelArgs &a, const uint32_t *src,
-                          const int32_t *label, const int32_t *cnt, uint8_t *sing, const ListArgs *lists,
-                          uint64_t *stats, bool inverse, hipStream_t st)
+hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32_t *src, const uint32_t *lab,
+                          const int32_t *cnt, uint8_t *sing, const ListArgs *lists, uint64_t *stats, bool inverse,
+                          hipStream_t st)
 {
-    Tmp T{t.x, t.y, t.z, t.vx, t.vy, t.vz, t.m, t.orig, t.lab};
     const int nb = nblocks(a.nact, 1 << 30);
-    if (!inverse) {
-        hipLaunchKernelGGL(k_gather, dim3(nb), dim3(TPB), 0, st, W, T, a.seg, a.act_off, a.nseg, a.nact, src, label,
-                           cnt, sing);
-        Lists L{};
-        int with = 0;
-        if (lists) {
-            with = 1;
-            L.pairs = lists->pairs;
-            for (int b = 0; b < 4; ++b) L.small[b] = lists->small[b];
-            L.big = lists->big;
-            L.count = lists->count;
-            L.cap_pairs = lists->cap_pairs;
-            L.cap_small = lists->cap_small;
-            L.cap_big = lists->cap_big;
-            L.small_max = lists->small_max;
-            for (int b = 0; b < 3; ++b) L.bin_lim[b] = lists->bin_lim[b];
-            L.labp = lists->labp;
-            L.singp = lists->singp;
-            L.errf = lists->errf;
-        }
-        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(TPB), 0, st, W, T, a.seg, a.act_off, a.nseg, a.nact,
-                           (const uint32_t *)nullptr, cnt, L, with, stats);
-    } else {
-        hipLaunchKernelGGL(k_gather, dim3(nb), dim3(TPB), 0, st, W, T, a.seg, a.act_off, a.nseg, a.nact,
-                           (const uint32_t *)nullptr, (const int32_t *)nullptr, (const int32_t *)nullptr,
-                           (uint8_t *)nullptr);
-        Lists L{};
-        hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(TPB), 0, st, W, T, a.seg, a.act_off, a.nseg, a.nact, src, cnt, L,
-                           0, stats);
+    if (inverse) {
+        hipLaunchKernelGGL(k_unpermute, dim3(nb), dim3(TPB), 0, st, from, to, a.seg, a.act_off, a.nseg, a.nact, src);
+        return hipGetLastError();
     }
+    Lists L{};
+    int with = 0;
+    if (lists) {
+        with = 1;
+        L.pairs = lists->pairs;
+        for (int b = 0; b < 4; ++b) L.small[b] = lists->small[b];
+        L.big = lists->big;
+        L.count = lists->count;
+        L.cap_pairs = lists->cap_pairs;
+        L.cap_small = lists->cap_small;
+        L.cap_big = lists->cap_big;
+        L.small_max = lists->small_max;
+        for (int b = 0; b < 3; ++b) L.bin_lim[b] = lists->bin_lim[b];
+        L.labp = lists->labp;
+        L.singp = lists->singp;
+        L.errf = lists->errf;
+    }
+    hipLaunchKernelGGL(k_permute, dim3(nb), dim3(TPB), 0, st, from, to, a.seg, a.act_off, a.nseg, a.nact, src, lab, cnt,
+                       sing, L, with, stats);
     return hipGetLastError();
 }
 

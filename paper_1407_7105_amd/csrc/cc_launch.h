@@ -19,11 +19,6 @@ struct GridLevelArgs {
     int32_t epoch;             // marks this visit's non-star flags (no clearing between visits)
 };
 
-struct TmpArrays {
-    double *x, *y, *z, *vx, *vy, *vz, *m;
-    int32_t *orig, *lab;
-};
-
 struct ListArgs {
     Seg *pairs;
     Seg *small[4];
@@ -67,12 +62,13 @@ hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t 
 size_t sort_temp_bytes(int n);
 hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, uint32_t *keys_out,
                        const uint32_t *vals_in, uint32_t *vals_out, int n, int end_bit, hipStream_t st);
-// forward (inverse == false): W[act(k)] <- W[src[k]]; with `label`, also the
-// entry-order singleton flags, and with `lists` the component work lists.
-// inverse: W[src[k]] <- W[act(k)].
-hipError_t launch_permute(SoA W, const TmpArrays &t, const GridLevelArgs &a, const uint32_t *src,
-                          const int32_t *label, const int32_t *cnt, uint8_t *sing, const ListArgs *lists,
-                          uint64_t *stats, bool inverse, hipStream_t st);
+// Between the two working buffers.  forward (inverse == false):
+// to[act(k)] <- from[src[k]]; with `lab` (sorted labels), also the entry-order
+// singleton flags, and with `lists` the component work lists.  inverse:
+// to[src[k]] <- from[act(k)].
+hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32_t *src, const uint32_t *lab,
+                          const int32_t *cnt, uint8_t *sing, const ListArgs *lists, uint64_t *stats, bool inverse,
+                          hipStream_t st);
 hipError_t launch_drift_seg(SoA W, const GridLevelArgs &a, const uint8_t *sing, double hh, uint64_t *stats,
                             hipStream_t st);
 hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, double h, double eps2, double G,
