@@ -3,11 +3,11 @@
 // cc_evolve keeps a working copy of the state.  One global step runs
 // evolve_cc(all, dt) (Fig. 2):
 //   * sets larger than the on-chip limit are split by grid-wide kernels
-//     (star test, all-pairs sweep with union-find, labels, a stable sort by
-//     label that makes every component contiguous), their sub-components are
-//     evolved for h/2 -- two-particle ones by the pair kernel, small ones by
-//     the on-chip kernel, large ones by recursing here -- and the level's
-//     drift/kick/drift runs between the two halves in the level's entry order;
+//     (all-pairs sweep with union-find that also takes the star test, labels,
+//     a stable sort by label that makes every component contiguous), their
+//     sub-components are evolved for h/2 -- two-particle ones by the pair
+//     kernel, small ones by the on-chip kernel, large ones by recursing here
+//     -- and the level's drift/kick/drift runs between the two halves;
 //   * every level restores its entry slot order before it returns, so each
 //     set is always visited in ascending particle index and every kick sums
 //     its partners in the same order as a sequential i<j sweep.
@@ -176,7 +176,7 @@ bool mixed(const cc_ctx *c) { return c->params.precision == CC_MIXED; }
 // The mixed path sums kicks over parallel tiles; EXACT order applies to FP64.
 bool exact_order(const cc_ctx *c) { return !mixed(c) && c->params.kick_order == CC_ORDER_EXACT; }
 
-// FP32 screen in front of the FP64 one in the grid-wide star test and sweep
+// FP32 screen in front of the FP64 one in the grid-wide sweep
 bool screen32(const cc_ctx *c) { return c->params.screen == CC_SCREEN_FP32; }
 
 int check_params(cc_ctx *c, const cc_params *p)
@@ -233,7 +233,7 @@ int ensure_capacity(cc_ctx *c, size_t n, size_t ncl)
         RC(dalloc(c, &c->keys_out, cap));
         RC(dalloc(c, &c->vals, cap));
         RC(dalloc(c, &c->parent, cap * PARENT_STRIDE));  // one entry per 128-byte line
-        RC(dalloc(c, &c->cnt, cap));
+        RC(dalloc(c, &c->cnt, 2 * cap));  // component sizes, one array per level parity
         RC(dalloc(c, &c->kick_acc, 3 * cap));
         size_t sb = sort_temp_bytes((int)cap);
         if (c->sort_temp) hipFree(c->sort_temp);
@@ -304,6 +304,10 @@ SoA work_soa(cc_ctx *c, int parity)
     if (parity & 1) return SoA{c->tmp[0], c->tmp[1], c->tmp[2], c->tmp[3], c->tmp[4], c->tmp[5], c->tmp[6], c->tmp_orig};
     return SoA{c->w[0], c->w[1], c->w[2], c->w[3], c->w[4], c->w[5], c->w[6], c->orig};
 }
+
+// Component-size counters of grid depth k (two arrays, by parity: a level
+// resets the next level's while it still reads its own).
+int32_t *cnt_of(cc_ctx *c, int k) { return c->cnt + (size_t)(k & 1) * c->cap; }
 
 SoA user_soa(const cc_state *s)
 {
@@ -646,18 +650,13 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
                     next_epoch(c)};
     const bool exact = exact_order(c);
     {
-        Span s(c, F_STAR);
-        HIPCHK(launch_star(W, a, lv.notstar, c->parent, c->cnt, p, h, screen32(c), c->stats, fam_ptr(c, F_STAR),
-                           c->st));
-    }
-    {
         Span s(c, F_SWEEP);
         HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, c->stats,
                             fam_ptr(c, F_SWEEP), c->st));
     }
     {
         Span s(c, F_LABEL);
-        HIPCHK(launch_label(a, lv.notstar, c->parent, lv.label, c->cnt, c->keys, c->vals, lv.count, c->stats,
+        HIPCHK(launch_label(a, lv.notstar, c->parent, lv.label, cnt_of(c, k), c->keys, c->vals, lv.count, c->stats,
                             c->st));
     }
     int bits = 0;
@@ -686,7 +685,8 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     L.errf = c->errf;
     {
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(W, Wp, a, lv.src, c->keys_out, c->cnt, lv.sing, &L, c->stats, false, c->st));
+        HIPCHK(launch_permute(W, Wp, a, lv.src, c->keys_out, cnt_of(c, k), lv.sing, &L, c->parent,
+                              cnt_of(c, k + 1), c->stats, false, c->st));
     }
     if (!exact) {
         // The singletons' first drift touches no particle of a component, so
@@ -733,13 +733,14 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
             // the kick, then the second drift of the singletons (fused)
             Span s(c, F_KICK);
             HIPCHK(launch_kick_tiles(Wp, a, kblk, nblk, kjob, njobs, ktile, lv2.labp, lv2.singp, h, c->params.eps2,
-                                     c->params.G, mixed(c), c->kick_part, c->errf, c->stats, fam_ptr(c, F_KICK),
-                                     c->st));
+                                     c->params.G, mixed(c), c->kick_part, c->parent, cnt_of(c, k + 1), c->errf,
+                                     c->stats, fam_ptr(c, F_KICK), c->st));
         }
         if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
         Level &lv3 = c->levels[k];
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(Wp, W, a, lv3.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
+        HIPCHK(launch_permute(Wp, W, a, lv3.src, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats, true,
+                              c->st));
         return CC_OK;
     }
 
@@ -749,7 +750,8 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     {
         Level &lv2 = c->levels[k];
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
+        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats, true,
+                              c->st));
     }
     {
         Level &lv2 = c->levels[k];
@@ -772,12 +774,14 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         {
             Level &lv2 = c->levels[k];
             Span s(c, F_PERMUTE);
-            HIPCHK(launch_permute(W, Wp, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, false, c->st));
+            HIPCHK(launch_permute(W, Wp, a, lv2.src, nullptr, nullptr, nullptr, nullptr, c->parent, cnt_of(c, k + 1),
+                                  c->stats, false, c->st));
         }
         RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
         Level &lv2 = c->levels[k];
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, c->cnt, nullptr, nullptr, c->stats, true, c->st));
+        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats, true,
+                              c->st));
     }
     return CC_OK;
 }
@@ -825,7 +829,13 @@ int global_step(cc_ctx *c, const std::vector<Seg> &top, double dt)
     RC(route_top(c, top, big, n_pairs, n_small));
     if (n_pairs + n_small[0] + n_small[1] + n_small[2] + n_small[3] > 0)
         RC(run_small_and_pairs(c, 0, c->levels[0], dt, n_pairs, n_small, c->st, 0));
-    if (!big.empty()) RC(evolve_grid(c, 0, big, dt));
+    if (!big.empty()) {
+        // the union-find of the top level; deeper levels are reset on the way
+        int end = 0;
+        for (const Seg &g : big) end = std::max(end, g.start + g.n);
+        HIPCHK(launch_uf_init(c->parent, cnt_of(c, 0), end, c->st));
+        RC(evolve_grid(c, 0, big, dt));
+    }
     return CC_OK;
 }
 
@@ -1140,13 +1150,13 @@ int cc_split_labels(cc_ctx *c, const cc_state *s, int64_t n, double h, int32_t *
     HIPCHK(hipMemsetAsync(c->stats, 0, ST_N * sizeof(uint64_t), c->st));
     const DevParams p = dev_params(c);
     SoA S = user_soa(s);
-    HIPCHK(launch_star(S, a, lv.notstar, c->parent, c->cnt, p, h, screen32(c), c->stats, nullptr, c->st));
+    HIPCHK(launch_uf_init(c->parent, cnt_of(c, 0), (int)n, c->st));
     HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, c->stats, nullptr, c->st));
-    HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, c->cnt, nullptr, nullptr, nullptr, c->stats, c->st));
+    HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, cnt_of(c, 0), nullptr, nullptr, nullptr, c->stats, c->st));
     if (n_nontrivial_out) {
-        // roots carry their component size in cnt (zeroed for every slot by the star kernel)
+        // roots carry their component size in cnt (zeroed for every slot by the reset)
         std::vector<int32_t> cnt((size_t)n);
-        HIPCHK(hipMemcpyAsync(cnt.data(), c->cnt, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipMemcpyAsync(cnt.data(), cnt_of(c, 0), (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
         HIPCHK(hipStreamSynchronize(c->st));
         int64_t nt = 0;
         for (int64_t i = 0; i < n; ++i) nt += (cnt[(size_t)i] >= 2);

@@ -210,43 +210,22 @@ __global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v)
 // chunks of TPB (chunk_off) and over triangular tile pairs (tile_off).
 // ---------------------------------------------------------------------------
 
-// Star test (Sec. 2.3, fully connected case): with X the segment's first slot,
-// the segment is one component if tau(X,U) < h for every other U.  notstar[s]
-// is set when some U fails.  Also initialises the union-find arrays.
-template <bool MIXED>
-__global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg,
-                                               const int32_t *__restrict__ chunk_off, int nseg,
-                                               int32_t *__restrict__ notstar, int32_t epoch,
-                                               int32_t *__restrict__ parent, int32_t *__restrict__ cnt,
-                                               DevParams p, double h, uint64_t *stats, uint64_t *fam)
+// Union-find reset of slots [0, n): parent[u] = u, cnt[u] = 0.  Deeper
+// levels are reset by the kernels that precede their visits (the level's
+// forward permutation and its kick combine).
+__global__ void k_uf_init(int32_t *parent, int32_t *cnt, int n)
 {
-    __shared__ uint64_t sh[4];
-    const int s = find_seg(chunk_off, nseg, blockIdx.x);
-    const Seg g = seg[s];
-    const int local = (blockIdx.x - chunk_off[s]) * TPB + threadIdx.x;
-    const int X = g.start;
-    uint64_t ev = 0;
-    if (local < g.n) {
-        const int u = g.start + local;
+    for (int u = blockIdx.x * TPB + threadIdx.x; u < n; u += gridDim.x * TPB) {
         *pslot(parent, u) = u;
         cnt[u] = 0;
-        if (local > 0) {
-            ev = 1;
-            if (!edge_decide<MIXED>(S.x[X] - S.x[u], S.y[X] - S.y[u], S.z[X] - S.z[u], S.vx[X] - S.vx[u],
-                                    S.vy[X] - S.vy[u], S.vz[X] - S.vz[u], S.m[X] + S.m[u], p,
-                                    screen_params(p, h), ccs::screen64_params(p.eta, h), h))
-                notstar[s] = epoch;
-        }
-    }
-    const uint64_t t = block_sum_u64(ev, sh);
-    if (threadIdx.x == 0) {
-        stat_add(stats, g.cluster, ST_TAU, t);
-        fam_add(fam, 0, t);
     }
 }
 
-// All-pairs sweep of a segment that failed the star test: for each pair
-// i<j with tau(i,j) < h, merge their sets.  Work is cut into 64x64 tiles
+// All-pairs sweep of a segment: for each pair i<j with tau(i,j) < h, merge
+// their sets.  The tiles of the first row also take the star test of Sec. 2.3
+// (the set is fully connected when its first slot X has tau(X,U) < h with
+// every other U): a tile that sees X miss one of its partners marks the
+// segment in notstar (the test only sets the algorithmic work count).  Work is cut into 64x64 tiles
 // (i tile <= j tile), one per wavefront, four per block.  A wavefront stages
 // its j tile in LDS, joins edges in a union-find local to the tile over its
 // 128 particles (64 when i tile = j tile), skipping an edge whose particles
@@ -266,7 +245,7 @@ constexpr int ST = 64;  // sweep tile edge (one wavefront)
 template <bool MIXED, int JS>
 __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ seg,
                                                 const int32_t *__restrict__ tile_off, int nseg,
-                                                const int32_t *__restrict__ notstar, int32_t epoch,
+                                                int32_t *__restrict__ notstar, int32_t epoch,
                                                 int32_t *__restrict__ parent, DevParams p, double h,
                                                 uint64_t *stats, uint64_t *fam)
 {
@@ -282,11 +261,8 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
     const int tile = blockIdx.x * TPW + ts;
     const int total = tile_off[nseg];
     int s = 0, ti = 0, tj = 0, T = 0;
-    bool active = tile < total;
-    if (active) {
-        s = find_seg(tile_off, nseg, tile);
-        active = notstar[s] == epoch;
-    }
+    const bool active = tile < total;
+    if (active) s = find_seg(tile_off, nseg, tile);
     Seg g{0, 0, 0, 0};
     if (active) {
         g = seg[s];
@@ -360,6 +336,11 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
                           vzi - jvz[w][jj], mi + jm[w][jj], p, h))
                 emask |= 1ull << jj;
         }
+        if (ti == 0 && lane == 0) {
+            // star test: X = the segment's first slot against this wave's partners
+            const uint64_t all = keep & (jnw >= 64 ? ~0ull : ((1ull << jnw) - 1ull));
+            if (emask != all) notstar[s] = epoch;
+        }
         const int32_t gi = gr[lane];
         int32_t lr = lane;  // an ancestor of this particle in the local structure
         const int joff = (diag ? 0 : ST) + j0w;
@@ -405,7 +386,7 @@ __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, cons
     int32_t l = -1;
     if (valid) {
         const int u = g.start + local;
-        l = ns ? gfind(parent, u) : g.start;
+        l = gfind(parent, u);
         label[u] = l;
         if (keys) {
             const int k = act_off[s] + local;
@@ -449,6 +430,7 @@ struct Lists {
 // Forward permutation of a level between the two working buffers: the k-th
 // active particle in (label, slot) order, from slot src[k] of `from`, goes to
 // its segment's k-th slot of `to`, so that every component is contiguous.
+// It also resets the union-find of those slots for the next level.
 // With `lab` (the sorted labels) it also records the singleton flags in entry
 // order, and with the lists the component-contiguous labels and singleton
 // flags and the level's work lists (pairs, small components by size, big
@@ -456,13 +438,17 @@ struct Lists {
 __global__ void k_permute(SoA from, SoA to, const Seg *__restrict__ seg, const int32_t *__restrict__ act_off,
                           int nseg, int nact, const uint32_t *__restrict__ src, const uint32_t *__restrict__ lab,
                           const int32_t *__restrict__ cnt, uint8_t *__restrict__ sing, Lists L, int with_lists,
-                          uint64_t *stats)
+                          int32_t *__restrict__ parent, int32_t *__restrict__ cnt_next, uint64_t *stats)
 {
     const int k = blockIdx.x * TPB + threadIdx.x;
     if (k >= nact) return;
     const int s = find_seg(act_off, nseg, k);
     const int dst = seg[s].start + (k - act_off[s]);
     const int u = (int)src[k];
+    // union-find reset for the next level's visits (its counters are the
+    // other parity's, so no read of cnt here races with the reset)
+    *pslot(parent, dst) = dst;
+    cnt_next[dst] = 0;
     to.x[dst] = from.x[u];
     to.y[dst] = from.y[u];
     to.z[dst] = from.z[u];
@@ -498,6 +484,20 @@ __global__ void k_permute(SoA from, SoA to, const Seg *__restrict__ seg, const i
         const int i = atomicAdd(&L.count[5], 1);
         if (i < L.cap_big) L.big[i] = c;
     }
+}
+
+// A level's report -- 8 counters and the big-component list -- copied into
+// coherent host memory, then `seq` published in the host flag: the host polls
+// the flag instead of waiting for the stream.  One block.
+__global__ __launch_bounds__(TPB) void k_report(const int32_t *__restrict__ rep, int32_t *host_rep, int cap_big,
+                                                uint32_t *host_flag, uint32_t seq)
+{
+    const int nb = min(max(rep[5], 0), cap_big);
+    const int n = 8 + nb * (int)(sizeof(Seg) / sizeof(int32_t));
+    for (int i = threadIdx.x; i < n; i += TPB) host_rep[i] = rep[i];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(host_flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Inverse permutation: the k-th slot of its segment in `from` goes back to
@@ -703,12 +703,14 @@ __global__ __launch_bounds__(TPB) void k_kick_reduce(const KickJob *__restrict__
 }
 
 // Adds the partial accelerations of every i in slot order, applies the kick,
-// then the drift D_{hh} of the singletons that ends the level's D K D.
+// then the drift D_{hh} of the singletons that ends the level's D K D; also
+// resets the union-find of the level's slots for the second half.
 __global__ __launch_bounds__(TPB) void k_kick_combine(SoA W, const Seg *__restrict__ seg,
                                                        const int32_t *__restrict__ chunk_off,
                                                        const KickTile *__restrict__ ktile, int nseg,
                                                        const double *__restrict__ part, double h,
                                                        const uint8_t *__restrict__ sing, double hh,
+                                                       int32_t *__restrict__ parent, int32_t *__restrict__ cnt_next,
                                                        uint64_t *stats)
 {
     __shared__ uint64_t sh[4];
@@ -718,6 +720,9 @@ __global__ __launch_bounds__(TPB) void k_kick_combine(SoA W, const Seg *__restri
     const int il = I * TPB + threadIdx.x;
     uint64_t drifted = 0;
     if (il < g.n) {
+        // union-find reset for the second-half visits of the next level
+        *pslot(parent, g.start + il) = g.start + il;
+        cnt_next[g.start + il] = 0;
         const KickTile kt = ktile[blockIdx.x];
         const double *pb = part + (size_t)kt.src * 3 * TPB;
         double ax = 0.0, ay = 0.0, az = 0.0;
@@ -1549,19 +1554,14 @@ hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, int32_t *cnt, DevParams p,
-                       double h, bool mixed, uint64_t *stats, uint64_t *fam, hipStream_t st)
+hipError_t launch_uf_init(int32_t *parent, int32_t *cnt, int n, hipStream_t st)
 {
-    if (mixed)
-        hipLaunchKernelGGL(k_star<true>, dim3(a.nchunks), dim3(TPB), 0, st, S, a.seg, a.chunk_off, a.nseg, notstar,
-                           a.epoch, parent, cnt, p, h, stats, fam);
-    else
-        hipLaunchKernelGGL(k_star<false>, dim3(a.nchunks), dim3(TPB), 0, st, S, a.seg, a.chunk_off, a.nseg, notstar,
-                           a.epoch, parent, cnt, p, h, stats, fam);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_uf_init, dim3(nblocks(n, 4096)), dim3(TPB), 0, st, parent, cnt, n);
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, DevParams p, double h,
+hipError_t launch_sweep(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, DevParams p, double h,
                         bool mixed, int split_tiles, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
     if (a.ntiles == 0) return hipSuccess;
@@ -1614,8 +1614,8 @@ hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, u
 }
 
 hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32_t *src, const uint32_t *lab,
-                          const int32_t *cnt, uint8_t *sing, const ListArgs *lists, uint64_t *stats, bool inverse,
-                          hipStream_t st)
+                          const int32_t *cnt, uint8_t *sing, const ListArgs *lists, int32_t *parent,
+                          int32_t *cnt_next, uint64_t *stats, bool inverse, hipStream_t st)
 {
     const int nb = nblocks(a.nact, 1 << 30);
     if (inverse) {
@@ -1640,7 +1640,14 @@ hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32
         L.errf = lists->errf;
     }
     hipLaunchKernelGGL(k_permute, dim3(nb), dim3(TPB), 0, st, from, to, a.seg, a.act_off, a.nseg, a.nact, src, lab, cnt,
-                       sing, L, with, stats);
+                       sing, L, with, parent, cnt_next, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_report(const int32_t *rep, int32_t *host_rep, int cap_big, uint32_t *host_flag, uint32_t seq,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL(k_report, dim3(1), dim3(TPB), 0, st, rep, host_rep, cap_big, host_flag, seq);
     return hipGetLastError();
 }
 
@@ -1662,8 +1669,8 @@ hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, 
 
 hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk, int nblk, const KickJob *jobs,
                              int njobs, const KickTile *ktile, const int32_t *labp, const uint8_t *singp, double h,
-                             double eps2, double G, bool mixed, double *part, int32_t *err, uint64_t *stats,
-                             uint64_t *fam, hipStream_t st)
+                             double eps2, double G, bool mixed, double *part, int32_t *parent, int32_t *cnt_next,
+                             int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
     if (nblk > 0) {
         if (mixed)
@@ -1675,7 +1682,7 @@ hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk
     }
     if (njobs > 0) hipLaunchKernelGGL(k_kick_reduce, dim3(njobs), dim3(TPB), 0, st, jobs, part);
     hipLaunchKernelGGL(k_kick_combine, dim3(a.nchunks), dim3(TPB), 0, st, W, a.seg, a.chunk_off, ktile, a.nseg,
-                       (const double *)part, h, singp, 0.5 * h, stats);
+                       (const double *)part, h, singp, 0.5 * h, parent, cnt_next, stats);
     return hipGetLastError();
 }
 

@@ -48,12 +48,12 @@ hipError_t launch_drift_mask(SoA S, int64_t n, const uint8_t *mask, double h, hi
 hipError_t launch_iota(int32_t *a, int64_t n, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t st);
 
+// Union-find reset of slots [0, n) (parent[u] = u, cnt[u] = 0).
+hipError_t launch_uf_init(int32_t *parent, int32_t *cnt, int n, hipStream_t st);
 // screen32: FP32 screen in front of the FP64 one (the template flag MIXED of
-// the kernels' edge test)
-hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, int32_t *cnt, DevParams p,
-                       double h, bool screen32, uint64_t *stats, uint64_t *fam, hipStream_t st);
-// split_tiles: launches of at most this many tiles take one block per tile
-hipError_t launch_sweep(SoA S, const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, DevParams p, double h,
+// the kernels' edge test); split_tiles: launches of at most this many tiles
+// take one block per tile
+hipError_t launch_sweep(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, DevParams p, double h,
                         bool screen32, int split_tiles, uint64_t *stats, uint64_t *fam, hipStream_t st);
 // labels and component sizes; with keys/vals the sort keys of the active
 // particles, with count the work-list counters cleared
@@ -67,8 +67,12 @@ hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, u
 // singleton flags, and with `lists` the component work lists.  inverse:
 // to[src[k]] <- from[act(k)].
 hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32_t *src, const uint32_t *lab,
-                          const int32_t *cnt, uint8_t *sing, const ListArgs *lists, uint64_t *stats, bool inverse,
-                          hipStream_t st);
+                          const int32_t *cnt, uint8_t *sing, const ListArgs *lists, int32_t *parent,
+                          int32_t *cnt_next, uint64_t *stats, bool inverse, hipStream_t st);
+// Copies a level's report (8 counters, then the big list) into host memory
+// and then writes seq to *host_flag (both host-mapped, coherent).
+hipError_t launch_report(const int32_t *rep, int32_t *host_rep, int cap_big, uint32_t *host_flag, uint32_t seq,
+                         hipStream_t st);
 hipError_t launch_drift_seg(SoA W, const GridLevelArgs &a, const uint8_t *sing, double hh, uint64_t *stats,
                             hipStream_t st);
 hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, double h, double eps2, double G,
@@ -79,8 +83,8 @@ hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, 
 // closing drift.
 hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk, int nblk, const KickJob *jobs,
                              int njobs, const KickTile *ktile, const int32_t *labp, const uint8_t *singp, double h,
-                             double eps2, double G, bool mixed, double *part, int32_t *err, uint64_t *stats,
-                             uint64_t *fam, hipStream_t st);
+                             double eps2, double G, bool mixed, double *part, int32_t *parent, int32_t *cnt_next,
+                             int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
 hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, double *ax, double *ay,
                            double *az, int32_t *err, hipStream_t st);
 hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, const double *az, double h,
