@@ -486,20 +486,6 @@ __global__ void k_permute(SoA from, SoA to, const Seg *__restrict__ seg, const i
     }
 }
 
-// A level's report -- 8 counters and the big-component list -- copied into
-// coherent host memory, then `seq` published in the host flag: the host polls
-// the flag instead of waiting for the stream.  One block.
-__global__ __launch_bounds__(TPB) void k_report(const int32_t *__restrict__ rep, int32_t *host_rep, int cap_big,
-                                                uint32_t *host_flag, uint32_t seq)
-{
-    const int nb = min(max(rep[5], 0), cap_big);
-    const int n = 8 + nb * (int)(sizeof(Seg) / sizeof(int32_t));
-    for (int i = threadIdx.x; i < n; i += TPB) host_rep[i] = rep[i];
-    __threadfence_system();
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(host_flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
 // Inverse permutation: the k-th slot of its segment in `from` goes back to
 // slot src[k] of `to` (entry order).
 __global__ void k_unpermute(SoA from, SoA to, const Seg *__restrict__ seg, const int32_t *__restrict__ act_off,
@@ -1641,13 +1627,6 @@ hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32
     }
     hipLaunchKernelGGL(k_permute, dim3(nb), dim3(TPB), 0, st, from, to, a.seg, a.act_off, a.nseg, a.nact, src, lab, cnt,
                        sing, L, with, parent, cnt_next, stats);
-    return hipGetLastError();
-}
-
-hipError_t launch_report(const int32_t *rep, int32_t *host_rep, int cap_big, uint32_t *host_flag, uint32_t seq,
-                         hipStream_t st)
-{
-    hipLaunchKernelGGL(k_report, dim3(1), dim3(TPB), 0, st, rep, host_rep, cap_big, host_flag, seq);
     return hipGetLastError();
 }
 

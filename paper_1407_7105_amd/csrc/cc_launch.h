@@ -69,10 +69,6 @@ hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, u
 hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32_t *src, const uint32_t *lab,
                           const int32_t *cnt, uint8_t *sing, const ListArgs *lists, int32_t *parent,
                           int32_t *cnt_next, uint64_t *stats, bool inverse, hipStream_t st);
-// Copies a level's report (8 counters, then the big list) into host memory
-// and then writes seq to *host_flag (both host-mapped, coherent).
-hipError_t launch_report(const int32_t *rep, int32_t *host_rep, int cap_big, uint32_t *host_flag, uint32_t seq,
-                         hipStream_t st);
 hipError_t launch_drift_seg(SoA W, const GridLevelArgs &a, const uint8_t *sing, double hh, uint64_t *stats,
                             hipStream_t st);
 hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, double h, double eps2, double G,
