@@ -685,15 +685,11 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     L.errf = c->errf;
     {
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(W, Wp, a, lv.src, c->keys_out, cnt_of(c, k), lv.sing, &L, c->parent,
-                              cnt_of(c, k + 1), c->stats, false, c->st));
-    }
-    if (!exact) {
-        // The singletons' first drift touches no particle of a component, so
-        // it may precede the first-half recursion: queued before the host
-        // waits for the report, it runs while the host reads it.
-        Span s(c, F_DRIFT);
-        HIPCHK(launch_drift_seg(Wp, a, lv.singp, 0.5 * h, c->stats, c->st));
+        // FAST order: the singletons' first drift touches no particle of a
+        // component, so it may precede the first-half recursion; it is
+        // applied by the permutation itself.
+        HIPCHK(launch_permute(W, Wp, a, lv.src, c->keys_out, cnt_of(c, k), lv.sing, &L, exact ? 0.0 : 0.5 * h,
+                              c->parent, cnt_of(c, k + 1), c->stats, false, c->st));
     }
     HIPCHK(hipMemcpyAsync(lv.h_rep, lv.rep, 8 * sizeof(int32_t) + (size_t)lv.cap_big * sizeof(Seg),
                           hipMemcpyDeviceToHost, c->st));
@@ -718,9 +714,9 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     }
 
     if (!exact) {
-        // Component-contiguous order throughout: (the first drift, queued
-        // above), the kick list, first half, kick and closing drift of the
-        // level, second half, then back to the entry order.
+        // Component-contiguous order throughout: (the first drift, done by
+        // the permutation), the kick list, first half, kick and closing drift
+        // of the level, second half, then back to the entry order.
         int nblk = 0, njobs = 0;
         RC(upload_kick_list(c, lv, segs, big, &nblk, &njobs));
         const KickTile *ktile = reinterpret_cast<const KickTile *>(lv.kick);
@@ -739,8 +735,8 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
         Level &lv3 = c->levels[k];
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(Wp, W, a, lv3.src, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats, true,
-                              c->st));
+        HIPCHK(launch_permute(Wp, W, a, lv3.src, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr, c->stats,
+                              true, c->st));
         return CC_OK;
     }
 
@@ -750,8 +746,8 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     {
         Level &lv2 = c->levels[k];
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats, true,
-                              c->st));
+        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr, c->stats,
+                              true, c->st));
     }
     {
         Level &lv2 = c->levels[k];
@@ -774,14 +770,14 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         {
             Level &lv2 = c->levels[k];
             Span s(c, F_PERMUTE);
-            HIPCHK(launch_permute(W, Wp, a, lv2.src, nullptr, nullptr, nullptr, nullptr, c->parent, cnt_of(c, k + 1),
-                                  c->stats, false, c->st));
+            HIPCHK(launch_permute(W, Wp, a, lv2.src, nullptr, nullptr, nullptr, nullptr, 0.0, c->parent,
+                                  cnt_of(c, k + 1), c->stats, false, c->st));
         }
         RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
         Level &lv2 = c->levels[k];
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->stats, true,
-                              c->st));
+        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr, c->stats,
+                              true, c->st));
     }
     return CC_OK;
 }

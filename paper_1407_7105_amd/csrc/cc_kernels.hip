@@ -430,59 +430,85 @@ struct Lists {
 // Forward permutation of a level between the two working buffers: the k-th
 // active particle in (label, slot) order, from slot src[k] of `from`, goes to
 // its segment's k-th slot of `to`, so that every component is contiguous.
-// It also resets the union-find of those slots for the next level.
-// With `lab` (the sorted labels) it also records the singleton flags in entry
-// order, and with the lists the component-contiguous labels and singleton
-// flags and the level's work lists (pairs, small components by size, big
-// components).  Reads and writes touch different buffers: one launch.
-__global__ void k_permute(SoA from, SoA to, const Seg *__restrict__ seg, const int32_t *__restrict__ act_off,
-                          int nseg, int nact, const uint32_t *__restrict__ src, const uint32_t *__restrict__ lab,
-                          const int32_t *__restrict__ cnt, uint8_t *__restrict__ sing, Lists L, int with_lists,
-                          int32_t *__restrict__ parent, int32_t *__restrict__ cnt_next, uint64_t *stats)
+// It also resets the union-find of those slots for the next level.  With
+// `lab` (the sorted labels) it records the singleton flags in entry order,
+// with the lists the component-contiguous labels and singleton flags and the
+// level's work lists (pairs, small components by size, big components), and
+// with drift_hh > 0 it applies the singletons' drift D_{hh} on the way (the
+// same operations as k_drift_seg).  Reads and writes touch different
+// buffers: one launch, one block per 256-slot chunk of a segment.
+__global__ __launch_bounds__(TPB) void k_permute(SoA from, SoA to, const Seg *__restrict__ seg,
+                                                  const int32_t *__restrict__ chunk_off,
+                                                  const int32_t *__restrict__ act_off, int nseg,
+                                                  const uint32_t *__restrict__ src, const uint32_t *__restrict__ lab,
+                                                  const int32_t *__restrict__ cnt, uint8_t *__restrict__ sing, Lists L,
+                                                  int with_lists, double drift_hh, int32_t *__restrict__ parent,
+                                                  int32_t *__restrict__ cnt_next, uint64_t *stats)
 {
-    const int k = blockIdx.x * TPB + threadIdx.x;
-    if (k >= nact) return;
-    const int s = find_seg(act_off, nseg, k);
-    const int dst = seg[s].start + (k - act_off[s]);
-    const int u = (int)src[k];
-    // union-find reset for the next level's visits (its counters are the
-    // other parity's, so no read of cnt here races with the reset)
-    *pslot(parent, dst) = dst;
-    cnt_next[dst] = 0;
-    to.x[dst] = from.x[u];
-    to.y[dst] = from.y[u];
-    to.z[dst] = from.z[u];
-    to.vx[dst] = from.vx[u];
-    to.vy[dst] = from.vy[u];
-    to.vz[dst] = from.vz[u];
-    to.m[dst] = from.m[u];
-    to.orig[dst] = from.orig[u];
-    if (!lab) return;
-    const int32_t l = (int32_t)lab[k];
-    if (sing) sing[u] = (cnt[l] == 1) ? 1 : 0;
-    if (!with_lists) return;
-    if (k == 0) L.count[7] = __hip_atomic_load(L.errf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (L.labp) {
-        L.labp[dst] = l;
-        L.singp[dst] = (cnt[l] == 1) ? 1 : 0;
-    }
-    const bool first = (k == act_off[s]) || ((int32_t)lab[k - 1] != l);
-    if (!first) return;
-    const int32_t size = cnt[l];
-    if (size < 2) return;
+    __shared__ uint64_t sh[4];
+    const int s = find_seg(chunk_off, nseg, blockIdx.x);
     const Seg g = seg[s];
-    stat_add(stats, g.cluster, ST_COMP, 1);
-    const Seg c = {dst, size, g.cluster, g.depth + 1};
-    if (size == 2) {
-        const int i = atomicAdd(&L.count[0], 1);
-        if (i < L.cap_pairs) L.pairs[i] = c;
-    } else if (size <= L.small_max) {
-        const int b = size <= L.bin_lim[0] ? 0 : size <= L.bin_lim[1] ? 1 : size <= L.bin_lim[2] ? 2 : 3;
-        const int i = atomicAdd(&L.count[1 + b], 1);
-        if (i < L.cap_small) L.small[b][i] = c;
-    } else {
-        const int i = atomicAdd(&L.count[5], 1);
-        if (i < L.cap_big) L.big[i] = c;
+    const int local = (blockIdx.x - chunk_off[s]) * TPB + threadIdx.x;
+    uint64_t drifted = 0;
+    if (local < g.n) {
+        const int k = act_off[s] + local;
+        const int dst = g.start + local;
+        const int u = (int)src[k];
+        // union-find reset for the next level's visits (its counters are
+        // the other parity's, so no read of cnt here races with the reset)
+        if (parent) {
+            *pslot(parent, dst) = dst;
+            cnt_next[dst] = 0;
+        }
+        const int32_t l = lab ? (int32_t)lab[k] : -1;
+        const bool single = lab && cnt[l] == 1;
+        double x = from.x[u], y = from.y[u], z = from.z[u];
+        const double vx = from.vx[u], vy = from.vy[u], vz = from.vz[u];
+        if (single && drift_hh > 0.0) {
+            x += drift_hh * vx;
+            y += drift_hh * vy;
+            z += drift_hh * vz;
+            drifted = 1;
+        }
+        to.x[dst] = x;
+        to.y[dst] = y;
+        to.z[dst] = z;
+        to.vx[dst] = vx;
+        to.vy[dst] = vy;
+        to.vz[dst] = vz;
+        to.m[dst] = from.m[u];
+        to.orig[dst] = from.orig[u];
+        if (lab) {
+            if (sing) sing[u] = single ? 1 : 0;
+            if (with_lists) {
+                if (k == 0) L.count[7] = __hip_atomic_load(L.errf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (L.labp) {
+                    L.labp[dst] = l;
+                    L.singp[dst] = single ? 1 : 0;
+                }
+                const bool first = (local == 0) || ((int32_t)lab[k - 1] != l);
+                const int32_t size = cnt[l];
+                if (first && size >= 2) {
+                    stat_add(stats, g.cluster, ST_COMP, 1);
+                    const Seg c = {dst, size, g.cluster, g.depth + 1};
+                    if (size == 2) {
+                        const int i = atomicAdd(&L.count[0], 1);
+                        if (i < L.cap_pairs) L.pairs[i] = c;
+                    } else if (size <= L.small_max) {
+                        const int b = size <= L.bin_lim[0] ? 0 : size <= L.bin_lim[1] ? 1 : size <= L.bin_lim[2] ? 2 : 3;
+                        const int i = atomicAdd(&L.count[1 + b], 1);
+                        if (i < L.cap_small) L.small[b][i] = c;
+                    } else {
+                        const int i = atomicAdd(&L.count[5], 1);
+                        if (i < L.cap_big) L.big[i] = c;
+                    }
+                }
+            }
+        }
+    }
+    if (drift_hh > 0.0) {  // uniform across the launch
+        const uint64_t t = block_sum_u64(drifted, sh);
+        if (threadIdx.x == 0) stat_add(stats, g.cluster, ST_DRIFT, t);
     }
 }
 
@@ -1600,8 +1626,8 @@ hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, u
 }
 
 hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32_t *src, const uint32_t *lab,
-                          const int32_t *cnt, uint8_t *sing, const ListArgs *lists, int32_t *parent,
-                          int32_t *cnt_next, uint64_t *stats, bool inverse, hipStream_t st)
+                          const int32_t *cnt, uint8_t *sing, const ListArgs *lists, double drift_hh,
+                          int32_t *parent, int32_t *cnt_next, uint64_t *stats, bool inverse, hipStream_t st)
 {
     const int nb = nblocks(a.nact, 1 << 30);
     if (inverse) {
@@ -1625,8 +1651,8 @@ hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32
         L.singp = lists->singp;
         L.errf = lists->errf;
     }
-    hipLaunchKernelGGL(k_permute, dim3(nb), dim3(TPB), 0, st, from, to, a.seg, a.act_off, a.nseg, a.nact, src, lab, cnt,
-                       sing, L, with, parent, cnt_next, stats);
+    hipLaunchKernelGGL(k_permute, dim3(a.nchunks), dim3(TPB), 0, st, from, to, a.seg, a.chunk_off, a.act_off, a.nseg,
+                       src, lab, cnt, sing, L, with, drift_hh, parent, cnt_next, stats);
     return hipGetLastError();
 }
 

@@ -64,11 +64,12 @@ hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, u
                        const uint32_t *vals_in, uint32_t *vals_out, int n, int end_bit, hipStream_t st);
 // Between the two working buffers.  forward (inverse == false):
 // to[act(k)] <- from[src[k]]; with `lab` (sorted labels), also the entry-order
-// singleton flags, and with `lists` the component work lists.  inverse:
-// to[src[k]] <- from[act(k)].
+// singleton flags, with `lists` the component work lists, with drift_hh > 0
+// the singletons' drift.  Forward resets the union-find of the slots (parent
+// and cnt_next) for the next level.  inverse: to[src[k]] <- from[act(k)].
 hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32_t *src, const uint32_t *lab,
-                          const int32_t *cnt, uint8_t *sing, const ListArgs *lists, int32_t *parent,
-                          int32_t *cnt_next, uint64_t *stats, bool inverse, hipStream_t st);
+                          const int32_t *cnt, uint8_t *sing, const ListArgs *lists, double drift_hh,
+                          int32_t *parent, int32_t *cnt_next, uint64_t *stats, bool inverse, hipStream_t st);
 hipError_t launch_drift_seg(SoA W, const GridLevelArgs &a, const uint8_t *sing, double hh, uint64_t *stats,
                             hipStream_t st);
 hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, double h, double eps2, double G,
