@@ -264,6 +264,35 @@ def test_evolve_grid_path_bitwise(n, small_max):
         assert st[k] == ost[k], (k, st[k], ost[k])
 
 
+def test_star_splits_counted_alike_on_grid_and_on_chip():
+    """A set whose first levels are fully connected (every pair step below the
+    pivot step, so the star test of Sec. 2.3 passes).  With an on-chip limit of
+    64 the sets of 65-128 bodies are split on the grid path, which takes the
+    star test in the sweep's first tile row; with 128 they are split on chip.
+    Both count n-1 pair steps per star split and n(n-1)/2 otherwise, so one
+    step gives the same algorithmic count, and states and statistics match the
+    oracle bit for bit."""
+    n = 300
+    s = random_set(n, 21)
+    p = oracle.Params(eta=0.01)
+    i, j = np.triu_indices(n, 1)
+    tau = oracle.pair_timesteps(s, i.astype(np.int32), j.astype(np.int32), p)
+    dt = 2.5 * float(tau.max())  # levels 0 and 1 (h = dt, dt/2) are stars
+    lab, nt, evals = oracle.split_labels(s, dt / 2, p)
+    assert nt == 1 and evals == n - 1
+    ref = s.copy()
+    rc, ost = oracle.evolve(ref, dt, dt, p)
+    runs = []
+    for small_max in (64, 128):
+        g = State.from_numpy(s)
+        st = ctx_for(p, small_max=small_max).evolve(g, dt, dt)
+        assert_state_equal(g.to_numpy(), ref, f"small_max={small_max}")
+        for k in STAT_KEYS:
+            assert st[k] == ost[k], (small_max, k, st[k], ost[k])
+        runs.append(st)
+    assert runs[0]["tau_pairs_alg"] == runs[1]["tau_pairs_alg"]
+
+
 def test_evolve_with_binaries_bitwise():
     s = synth.workload(5, n=1200)
     p = oracle.Params(eta=0.01)
