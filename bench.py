@@ -38,7 +38,7 @@ PEAK_FP64_VECTOR = 78.6e12   # MI355X: 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 SWEEP_TRAFFIC_BYTES = 11331494
 SWEEP_TRAFFIC_SOURCES = ("paper_1407_7105_amd/csrc/cc_kernels.hip", "paper_1407_7105_amd/csrc/cc_device.h",
                          "paper_1407_7105_amd/csrc/cc_screen64.h")
-SWEEP_TRAFFIC_SHA1 = "3de855aad66c94a8df408a475b11c64a6c8ba6c3"
+SWEEP_TRAFFIC_SHA1 = "288299b44f29a3ef1f74a91f2e35e8c1b46f4b85"
 
 
 def sweep_traffic():

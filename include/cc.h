@@ -80,7 +80,7 @@ typedef struct {
     int32_t small_max;      /* largest component integrated on chip (3..1024;
                                0 = library default, 128) */
     int32_t kick_order;     /* cc_kick_order */
-    int32_t screen;         /* cc_screen for the grid-wide star test and sweep; either
+    int32_t screen;         /* cc_screen for the grid-wide sweep; either
                                screen leaves undecided pairs to the literal FP64 formula,
                                so partitions do not depend on it */
 } cc_params;

@@ -225,8 +225,9 @@ __global__ void k_uf_init(int32_t *parent, int32_t *cnt, int n)
 // their sets.  The tiles of the first row also take the star test of Sec. 2.3
 // (the set is fully connected when its first slot X has tau(X,U) < h with
 // every other U): a tile that sees X miss one of its partners marks the
-// segment in notstar (the test only sets the algorithmic work count).  Work is cut into 64x64 tiles
-// (i tile <= j tile), one per wavefront, four per block.  A wavefront stages
+// segment in notstar (the test only sets the algorithmic work count).  Work
+// is cut into 64x64 tiles (i tile <= j tile), one per wavefront, four per
+// block.  A wavefront stages
 // its j tile in LDS, joins edges in a union-find local to the tile over its
 // 128 particles (64 when i tile = j tile), skipping an edge whose particles
 // already share the global root read at tile start, and finally merges each

@@ -13,10 +13,10 @@ namespace ccg {
 struct GridLevelArgs {
     const Seg *seg;
     const int32_t *chunk_off;  // prefix over ceil(n/256) slot chunks, nseg+1
-    const int32_t *tile_off;   // prefix over triangular 256x256 tiles (non-star sweep), nseg+1
+    const int32_t *tile_off;   // prefix over the sweep's triangular 64x64 tiles, nseg+1
     const int32_t *act_off;    // prefix over n, nseg+1
     int nseg, nchunks, ntiles, nact;
-    int32_t epoch;             // marks this visit's non-star flags (no clearing between visits)
+    int32_t epoch;             // marks this visit's not-a-star flags (no clearing between visits)
 };
 
 struct ListArgs {
