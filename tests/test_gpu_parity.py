@@ -478,6 +478,32 @@ def test_fast_once_per_pair_kick_with_components():
         assert st[k] == ost[k], (k, st[k], ost[k])
 
 
+def test_fast_order_batch_of_large_clusters():
+    """Four clusters above the on-chip limit in one batch: the grid levels hold
+    several segments at once, and the kick's block list (tiles inside a large
+    component skip it, work cut evenly over all segments, partial sums in two
+    stages where a tile has many blocks) spans them.  One global step agrees
+    with the oracle cluster by cluster to 1e-10 with the same decisions."""
+    sizes = [300, 1400, 150, 700]
+    parts = [synth.plummer(m, 500 + m, masses="salpeter") for m in sizes]
+    s = Particles.from_arrays(np.concatenate([q.pos() for q in parts]), np.concatenate([q.vel() for q in parts]),
+                              np.concatenate([q.m for q in parts]))
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    p = oracle.Params(eta=0.01)
+    ref = s.copy()
+    rc, osts = oracle.evolve_batch(ref, off, 1 / 64, 1 / 64, p)
+    g = State.from_numpy(s)
+    sts = ctx_for(p, kick_order=CC_ORDER_FAST, small_max=128).evolve_batch(g, off, 1 / 64, 1 / 64)
+    got = g.to_numpy()
+    for c in range(len(sizes)):
+        a, b = off[c], off[c + 1]
+        one = Particles.from_arrays(np.stack([getattr(ref, f)[a:b] for f in ("x", "y", "z")], 1),
+                                    np.stack([getattr(ref, f)[a:b] for f in ("vx", "vy", "vz")], 1), ref.m[a:b])
+        rel_close({f: got[f][a:b] for f in got}, one, 1e-10, f"cluster {c}")
+        for k in STAT_KEYS:
+            assert sts[c][k] == osts[c][k], (c, k, sts[c][k], osts[c][k])
+
+
 @pytest.mark.parametrize("cfg,n,small_max", [(1, None, 0), (2, 1500, 64), (5, 1200, 0)])
 def test_fast_order_one_step_lockstep(cfg, n, small_max):
     """One global step from the same state: the fast kick order agrees with
