@@ -39,8 +39,8 @@ constexpr int32_t DEFAULT_SWEEP_SPLIT = 2048;
 constexpr int32_t DEFAULT_KICK_GROUPS = 4;
 
 // kernel families for timing
-enum Fam { F_STAR, F_SWEEP, F_LABEL, F_SORT, F_PERMUTE, F_DRIFT, F_KICK, F_PAIRS, F_SMALL, F_VALIDATE, F_OTHER, F_N };
-const char *fam_name[F_N] = {"star", "sweep", "label", "sort", "permute", "drift",
+enum Fam { F_SWEEP, F_LABEL, F_SORT, F_PERMUTE, F_DRIFT, F_KICK, F_PAIRS, F_SMALL, F_VALIDATE, F_OTHER, F_N };
+const char *fam_name[F_N] = {"sweep", "label", "sort", "permute", "drift",
                              "kick", "pairs", "small", "validate", "other"};
 
 struct DevBuf {
