@@ -689,7 +689,7 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         // component, so it may precede the first-half recursion; it is
         // applied by the permutation itself.
         HIPCHK(launch_permute(W, Wp, a, lv.src, c->keys_out, cnt_of(c, k), lv.sing, &L, exact ? 0.0 : 0.5 * h,
-                              c->parent, cnt_of(c, k + 1), c->stats, false, c->st));
+                              c->parent, cnt_of(c, k + 1), fam_ptr(c, F_KICK), !exact, c->stats, false, c->st));
     }
     HIPCHK(hipMemcpyAsync(lv.h_rep, lv.rep, 8 * sizeof(int32_t) + (size_t)lv.cap_big * sizeof(Seg),
                           hipMemcpyDeviceToHost, c->st));
@@ -730,13 +730,13 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
             Span s(c, F_KICK);
             HIPCHK(launch_kick_tiles(Wp, a, kblk, nblk, kjob, njobs, ktile, lv2.labp, lv2.singp, h, c->params.eps2,
                                      c->params.G, mixed(c), c->kick_part, c->parent, cnt_of(c, k + 1), c->errf,
-                                     c->stats, fam_ptr(c, F_KICK), c->st));
+                                     c->stats, c->st));
         }
         if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
         Level &lv3 = c->levels[k];
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(Wp, W, a, lv3.src, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr, c->stats,
-                              true, c->st));
+        HIPCHK(launch_permute(Wp, W, a, lv3.src, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr, nullptr,
+                              false, c->stats, true, c->st));
         return CC_OK;
     }
 
@@ -746,8 +746,8 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     {
         Level &lv2 = c->levels[k];
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr, c->stats,
-                              true, c->st));
+        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr, nullptr,
+                              false, c->stats, true, c->st));
     }
     {
         Level &lv2 = c->levels[k];
@@ -771,13 +771,13 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
             Level &lv2 = c->levels[k];
             Span s(c, F_PERMUTE);
             HIPCHK(launch_permute(W, Wp, a, lv2.src, nullptr, nullptr, nullptr, nullptr, 0.0, c->parent,
-                                  cnt_of(c, k + 1), c->stats, false, c->st));
+                                  cnt_of(c, k + 1), nullptr, false, c->stats, false, c->st));
         }
         RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
         Level &lv2 = c->levels[k];
         Span s(c, F_PERMUTE);
-        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr, c->stats,
-                              true, c->st));
+        HIPCHK(launch_permute(Wp, W, a, lv2.src, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr, nullptr,
+                              false, c->stats, true, c->st));
     }
     return CC_OK;
 }

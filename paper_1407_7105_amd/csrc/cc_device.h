@@ -355,8 +355,9 @@ __device__ __forceinline__ bool accel_term_rsq(double xi, double yi, double zi, 
 
 // The same term behind a mask, for loops without a branch per partner: a
 // partner that is off (same component, or the particle itself) contributes a
-// zero factor whatever its distance, and raises no error.
-__device__ __forceinline__ bool accel_term_rsq_if(bool on, double xi, double yi, double zi, double xj, double yj,
+// zero factor whatever its distance.  A coincident pair that is on gives a
+// non-finite sum, which the caller checks once.
+__device__ __forceinline__ void accel_term_rsq_if(bool on, double xi, double yi, double zi, double xj, double yj,
                                                   double zj, double gmj, double eps2, double &ax, double &ay,
                                                   double &az)
 {
@@ -375,7 +376,6 @@ __device__ __forceinline__ bool accel_term_rsq_if(bool on, double xi, double yi,
     ax = __builtin_fma(f, dx, ax);
     ay = __builtin_fma(f, dy, ay);
     az = __builtin_fma(f, dz, az);
-    return !on || r2 != 0.0;
 }
 
 // ---------------------------------------------------------------------------

@@ -444,7 +444,8 @@ __global__ __launch_bounds__(TPB) void k_permute(SoA from, SoA to, const Seg *__
                                                   const uint32_t *__restrict__ src, const uint32_t *__restrict__ lab,
                                                   const int32_t *__restrict__ cnt, uint8_t *__restrict__ sing, Lists L,
                                                   int with_lists, double drift_hh, int32_t *__restrict__ parent,
-                                                  int32_t *__restrict__ cnt_next, uint64_t *stats)
+                                                  int32_t *__restrict__ cnt_next, uint64_t *kick_fam, int count_kick,
+                                                  uint64_t *stats)
 {
     __shared__ uint64_t sh[4];
     const int s = find_seg(chunk_off, nseg, blockIdx.x);
@@ -483,6 +484,12 @@ __global__ __launch_bounds__(TPB) void k_permute(SoA from, SoA to, const Seg *__
             if (sing) sing[u] = single ? 1 : 0;
             if (with_lists) {
                 if (k == 0) L.count[7] = __hip_atomic_load(L.errf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (count_kick && local == 0) {
+                    // the tiled kick's pairs: all of the segment's ...
+                    const uint64_t all = (uint64_t)g.n * (uint64_t)(g.n - 1) / 2;
+                    stat_add(stats, g.cluster, ST_KICK, all);
+                    fam_add(kick_fam, 1, all);
+                }
                 if (L.labp) {
                     L.labp[dst] = l;
                     L.singp[dst] = single ? 1 : 0;
@@ -491,6 +498,12 @@ __global__ __launch_bounds__(TPB) void k_permute(SoA from, SoA to, const Seg *__
                 const int32_t size = cnt[l];
                 if (first && size >= 2) {
                     stat_add(stats, g.cluster, ST_COMP, 1);
+                    if (count_kick) {
+                        // ... less those inside a component (modulo 2^64)
+                        const uint64_t in = (uint64_t)size * (uint64_t)(size - 1) / 2;
+                        stat_add(stats, g.cluster, ST_KICK, (uint64_t)0 - in);
+                        fam_add(kick_fam, 1, (uint64_t)0 - in);
+                    }
                     const Seg c = {dst, size, g.cluster, g.depth + 1};
                     if (size == 2) {
                         const int i = atomicAdd(&L.count[0], 1);
@@ -618,17 +631,17 @@ __global__ __launch_bounds__(TPB) void k_kick_seg(SoA W, const Seg *__restrict__
 // component that component itself (all of its pairs are inside it), and a j
 // tile inside the i tile's own component is skipped whole here.  Each block
 // writes its partial accelerations; k_kick_combine adds the blocks of every i
-// tile in list order, so the result is deterministic.
+// tile in list order, so the result is deterministic.  The pairs kicked are
+// counted by the forward permutation (n(n-1)/2 per segment less s(s-1)/2 per
+// component), not here.
 template <bool MIXED>
 __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict__ seg,
                                                      const KickBlock *__restrict__ blk,
                                                      const int32_t *__restrict__ labp, double eps2, double G,
-                                                     double *__restrict__ part, int32_t *err, uint64_t *stats,
-                                                     uint64_t *fam)
+                                                     double *__restrict__ part, int32_t *err)
 {
     __shared__ double jx[TPB], jy[TPB], jz[TPB], jm[TPB];
     __shared__ int32_t jl[TPB];
-    __shared__ uint64_t sh[4];
     const KickBlock kb = blk[blockIdx.x];
     const Seg g = seg[kb.seg];
     const int I = kb.itile;
@@ -641,7 +654,6 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
     const int ifirst = g.start + I * TPB, ilast = g.start + min(g.n, (I + 1) * TPB) - 1;
     const int32_t iu = (labp[ifirst] == labp[ilast]) ? labp[ifirst] : -1;
     double ax = 0.0, ay = 0.0, az = 0.0;
-    uint64_t pairs = 0;
     bool ok = true;
     for (int jb = jlo; jb < jhi; jb += TPB) {
         const int jn = min(TPB, jhi - jb);
@@ -666,22 +678,16 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
                 for (int jj = 0; jj < jn; ++jj) {
                     if (jl[jj] == li) continue;
                     ok &= accel_term32(xi, yi, zi, jx[jj], jy[jj], jz[jj], (float)jm[jj], e2, k);
-                    pairs += (jb + jj > il);
                 }
                 ax += (double)k.sx - (double)k.cx;
                 ay += (double)k.sy - (double)k.cy;
                 az += (double)k.sz - (double)k.cz;
             } else {
                 // no branch per partner: partners of the own component add
-                // a zero factor
-                uint32_t np = 0;
+                // a zero factor; a coincident pair shows as a non-finite sum
 #pragma unroll 2
-                for (int jj = 0; jj < jn; ++jj) {
-                    const bool on = jl[jj] != li;
-                    ok &= accel_term_rsq_if(on, xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, ax, ay, az);
-                    np += (on && jb + jj > il) ? 1u : 0u;
-                }
-                pairs += np;
+                for (int jj = 0; jj < jn; ++jj)
+                    accel_term_rsq_if(jl[jj] != li, xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, ax, ay, az);
             }
         }
     }
@@ -689,12 +695,8 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
     pb[threadIdx.x] = ax;
     pb[TPB + threadIdx.x] = ay;
     pb[2 * TPB + threadIdx.x] = az;
+    if (!MIXED) ok = isfinite(ax) && isfinite(ay) && isfinite(az);
     if (valid && !ok) atomicOr(err, EB_NONFINITE);
-    const uint64_t tot = block_sum_u64(pairs, sh);
-    if (threadIdx.x == 0) {
-        stat_add(stats, g.cluster, ST_KICK, tot);
-        fam_add(fam, 1, tot);
-    }
 }
 
 // Group sums of the two-stage reduction: job b adds its slots in order.
@@ -1628,7 +1630,8 @@ hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, u
 
 hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32_t *src, const uint32_t *lab,
                           const int32_t *cnt, uint8_t *sing, const ListArgs *lists, double drift_hh,
-                          int32_t *parent, int32_t *cnt_next, uint64_t *stats, bool inverse, hipStream_t st)
+                          int32_t *parent, int32_t *cnt_next, uint64_t *kick_fam, bool count_kick, uint64_t *stats,
+                          bool inverse, hipStream_t st)
 {
     const int nb = nblocks(a.nact, 1 << 30);
     if (inverse) {
@@ -1653,7 +1656,7 @@ hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32
         L.errf = lists->errf;
     }
     hipLaunchKernelGGL(k_permute, dim3(a.nchunks), dim3(TPB), 0, st, from, to, a.seg, a.chunk_off, a.act_off, a.nseg,
-                       src, lab, cnt, sing, L, with, drift_hh, parent, cnt_next, stats);
+                       src, lab, cnt, sing, L, with, drift_hh, parent, cnt_next, kick_fam, count_kick ? 1 : 0, stats);
     return hipGetLastError();
 }
 
@@ -1676,15 +1679,15 @@ hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, 
 hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk, int nblk, const KickJob *jobs,
                              int njobs, const KickTile *ktile, const int32_t *labp, const uint8_t *singp, double h,
                              double eps2, double G, bool mixed, double *part, int32_t *parent, int32_t *cnt_next,
-                             int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st)
+                             int32_t *err, uint64_t *stats, hipStream_t st)
 {
     if (nblk > 0) {
         if (mixed)
             hipLaunchKernelGGL(k_kick_tiles<true>, dim3(nblk), dim3(TPB), 0, st, W, a.seg, blk, labp, eps2, G, part,
-                               err, stats, fam);
+                               err);
         else
             hipLaunchKernelGGL(k_kick_tiles<false>, dim3(nblk), dim3(TPB), 0, st, W, a.seg, blk, labp, eps2, G, part,
-                               err, stats, fam);
+                               err);
     }
     if (njobs > 0) hipLaunchKernelGGL(k_kick_reduce, dim3(njobs), dim3(TPB), 0, st, jobs, part);
     hipLaunchKernelGGL(k_kick_combine, dim3(a.nchunks), dim3(TPB), 0, st, W, a.seg, a.chunk_off, ktile, a.nseg,

@@ -65,11 +65,13 @@ hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, u
 // Between the two working buffers.  forward (inverse == false):
 // to[act(k)] <- from[src[k]]; with `lab` (sorted labels), also the entry-order
 // singleton flags, with `lists` the component work lists, with drift_hh > 0
-// the singletons' drift.  Forward resets the union-find of the slots (parent
-// and cnt_next) for the next level.  inverse: to[src[k]] <- from[act(k)].
+// the singletons' drift, with count_kick the pairs the level's tiled kick
+// will kick (stats and kick_fam).  Forward resets the union-find of the slots
+// (parent and cnt_next) for the next level.  inverse: to[src[k]] <- from[act(k)].
 hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32_t *src, const uint32_t *lab,
                           const int32_t *cnt, uint8_t *sing, const ListArgs *lists, double drift_hh,
-                          int32_t *parent, int32_t *cnt_next, uint64_t *stats, bool inverse, hipStream_t st);
+                          int32_t *parent, int32_t *cnt_next, uint64_t *kick_fam, bool count_kick, uint64_t *stats,
+                          bool inverse, hipStream_t st);
 hipError_t launch_drift_seg(SoA W, const GridLevelArgs &a, const uint8_t *sing, double hh, uint64_t *stats,
                             hipStream_t st);
 hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, double h, double eps2, double G,
@@ -81,7 +83,7 @@ hipError_t launch_kick_seg(SoA W, const GridLevelArgs &a, const int32_t *label, 
 hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk, int nblk, const KickJob *jobs,
                              int njobs, const KickTile *ktile, const int32_t *labp, const uint8_t *singp, double h,
                              double eps2, double G, bool mixed, double *part, int32_t *parent, int32_t *cnt_next,
-                             int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
+                             int32_t *err, uint64_t *stats, hipStream_t st);
 hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, double *ax, double *ay,
                            double *az, int32_t *err, hipStream_t st);
 hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, const double *az, double h,
