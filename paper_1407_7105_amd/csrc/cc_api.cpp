@@ -440,6 +440,43 @@ int upload_desc(cc_ctx *c, Level &lv, int nseg)
     return CC_OK;
 }
 
+// A descriptor block: nseg segments, then the prefixes over 256-slot chunks,
+// over the sweep's triangular tiles and over slots (nseg+1 ints each).
+struct DescTotals {
+    int nchunks, ntiles, nact;
+};
+
+size_t desc_bytes(size_t nseg) { return nseg * sizeof(Seg) + 3 * (nseg + 1) * sizeof(int32_t); }
+
+int write_desc(cc_ctx *c, const std::vector<Seg> &segs, unsigned char *host, DescTotals *t)
+{
+    const size_t nseg = segs.size(), S1 = nseg + 1;
+    Seg *sg = reinterpret_cast<Seg *>(host);
+    int32_t *chunk = reinterpret_cast<int32_t *>(host + nseg * sizeof(Seg)), *tile = chunk + S1, *act = chunk + 2 * S1;
+    chunk[0] = tile[0] = act[0] = 0;
+    for (size_t s = 0; s < nseg; ++s) {
+        sg[s] = segs[s];
+        const int n = segs[s].n;
+        const int64_t T = (n + TPB - 1) / TPB;
+        const int64_t T64 = (n + SWEEP_TILE - 1) / SWEEP_TILE;
+        const int64_t nt = tile[s] + T64 * (T64 + 1) / 2;
+        if (nt > INT32_MAX) return fail(c, CC_ERR_ARG, "set of %d particles is too large", n);
+        chunk[s + 1] = chunk[s] + (int32_t)T;
+        tile[s + 1] = (int32_t)nt;
+        act[s + 1] = act[s] + n;
+    }
+    *t = DescTotals{chunk[nseg], tile[nseg], act[nseg]};
+    return CC_OK;
+}
+
+GridLevelArgs desc_args(const unsigned char *dev, int nseg, const DescTotals &t, int32_t epoch)
+{
+    const int32_t *offs = reinterpret_cast<const int32_t *>(dev + (size_t)nseg * sizeof(Seg));
+    const size_t S1 = (size_t)nseg + 1;
+    return GridLevelArgs{reinterpret_cast<const Seg *>(dev), offs, offs + S1, offs + 2 * S1, nseg, t.nchunks,
+                         t.ntiles, t.nact, epoch};
+}
+
 // A level's two-particle and small components in one launch.  Queue
 // counters are per level: the launch of a level may still run on the side
 // stream while a deeper level launches its own.  n_small[b] = items in size
@@ -470,7 +507,8 @@ int run_small_and_pairs(cc_ctx *c, int k, Level &lv, double H, int n_pairs, cons
     return CC_OK;
 }
 
-int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h);
+int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h,
+                const unsigned char *pre_desc = nullptr, const DescTotals *pre_tot = nullptr);
 
 // Kick blocks of one level visit, in the component-contiguous order: every
 // 256-slot i tile sees its whole segment, except that a tile lying inside one
@@ -479,11 +517,13 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h);
 // chosen so that the launch has about kick_groups blocks per compute unit of
 // equal work, wherever in the segments the work lies.  The list (a KickTile
 // per i tile, then the blocks) goes up with one copy on the main stream, and
-// the partial-acceleration buffer grows to the slot count.  A tile with more
+// the partial-acceleration buffer grows to the slot count.  The descriptor
+// block of the next level's sets (the large components) follows in the same
+// copy; both halves' visits of that level use it.  A tile with more
 // than KICK_FANIN blocks is summed in two stages: group sums of KICK_FANIN
 // consecutive blocks (KickJobs, slots after the blocks'), then the groups.
 int upload_kick_list(cc_ctx *c, Level &lv, const std::vector<Seg> &segs, const std::vector<Seg> &big, int *nblk_out,
-                     int *njobs_out)
+                     int *njobs_out, const unsigned char **child_desc, DescTotals *child_tot)
 {
     // per i tile, the partners [xlo, xhi) it leaves out (offsets within the
     // segment; empty when xlo == xhi)
@@ -528,7 +568,10 @@ int upload_kick_list(cc_ctx *c, Level &lv, const std::vector<Seg> &segs, const s
     }
     if (nblk + njobs > INT32_MAX) return fail(c, CC_ERR_ARG, "kick list too long");
     const size_t nslot = (size_t)(nblk + njobs);
-    const size_t bytes = ntile * sizeof(KickTile) + (size_t)nblk * sizeof(KickBlock) + (size_t)njobs * sizeof(KickJob);
+    const size_t kbytes = ntile * sizeof(KickTile) + (size_t)nblk * sizeof(KickBlock) + (size_t)njobs * sizeof(KickJob);
+    // the next level's descriptor block rides along (16-byte aligned)
+    const size_t doff = (kbytes + 15) & ~(size_t)15;
+    const size_t bytes = doff + (big.empty() ? 0 : desc_bytes(big.size()));
     if (lv.kick_pending) {
         HIPCHK(hipEventSynchronize(lv.kick_ev));
         lv.kick_pending = false;
@@ -576,6 +619,11 @@ int upload_kick_list(cc_ctx *c, Level &lv, const std::vector<Seg> &segs, const s
             }
         }
     }
+    *child_desc = nullptr;
+    if (!big.empty()) {
+        RC(write_desc(c, big, lv.h_kick + doff, child_tot));
+        *child_desc = lv.kick + doff;
+    }
     HIPCHK(hipMemcpyAsync(lv.kick, lv.h_kick, bytes, hipMemcpyHostToDevice, c->st));
     HIPCHK(hipEventRecord(lv.kick_ev, c->st));
     lv.kick_pending = true;
@@ -590,12 +638,12 @@ int upload_kick_list(cc_ctx *c, Level &lv, const std::vector<Seg> &segs, const s
 // into the latter on the main stream; the main stream waits for the side
 // stream before the level's own kick.
 int dispatch_sets(cc_ctx *c, int k, Level &lv, double H, const std::vector<Seg> &big, int n_pairs,
-                  const int n_small[4])
+                  const int n_small[4], const unsigned char *big_desc = nullptr, const DescTotals *big_tot = nullptr)
 {
     const bool on_chip = n_pairs + n_small[0] + n_small[1] + n_small[2] + n_small[3] > 0;
     if (!on_chip || big.empty()) {
         RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, c->st, k + 1));
-        if (!big.empty()) RC(evolve_grid(c, k + 1, big, H));
+        if (!big.empty()) RC(evolve_grid(c, k + 1, big, H, big_desc, big_tot));
         return CC_OK;
     }
     RC(order_streams(c, c->st, c->side));
@@ -603,7 +651,7 @@ int dispatch_sets(cc_ctx *c, int k, Level &lv, double H, const std::vector<Seg> 
     hipEvent_t done;
     RC(take_event(c, &done));
     HIPCHK(hipEventRecord(done, c->side));
-    RC(evolve_grid(c, k + 1, big, H));
+    RC(evolve_grid(c, k + 1, big, H, big_desc, big_tot));
     HIPCHK(hipStreamWaitEvent(c->st, done, 0));
     return CC_OK;
 }
@@ -617,7 +665,10 @@ bool trace_on()
     return on != 0;
 }
 
-int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
+// pre_desc: the sets' descriptor block already on the device (uploaded by the
+// parent level together with its kick list), with its totals.
+int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h, const unsigned char *pre_desc,
+                const DescTotals *pre_tot)
 {
     if (segs.empty()) return CC_OK;
     if (segs[0].depth > c->params.max_depth)
@@ -630,24 +681,15 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
     SoA Wp = work_soa(c, k + 1);  // the same slots, component-contiguous
 
     // segment descriptors and prefix arrays
-    const size_t S1 = (size_t)nseg + 1;
-    place_offsets(lv, nseg);
-    int32_t *chunk = lv.h_offs, *tile = lv.h_offs + S1, *act = lv.h_offs + 2 * S1;
-    chunk[0] = tile[0] = act[0] = 0;
-    for (int s = 0; s < nseg; ++s) {
-        lv.h_seg[s] = segs[s];
-        const int n = segs[s].n;
-        const int64_t T = (n + TPB - 1) / TPB;
-        const int64_t T64 = (n + SWEEP_TILE - 1) / SWEEP_TILE;
-        const int64_t nt = tile[s] + T64 * (T64 + 1) / 2;
-        if (nt > INT32_MAX) return fail(c, CC_ERR_ARG, "set of %d particles is too large", n);
-        chunk[s + 1] = chunk[s] + (int32_t)T;
-        tile[s + 1] = (int32_t)nt;
-        act[s + 1] = act[s] + n;
+    GridLevelArgs a{};
+    if (pre_desc) {
+        a = desc_args(pre_desc, nseg, *pre_tot, next_epoch(c));
+    } else {
+        DescTotals t{};
+        RC(write_desc(c, segs, lv.h_desc, &t));
+        RC(upload_desc(c, lv, nseg));
+        a = desc_args(lv.desc, nseg, t, next_epoch(c));
     }
-    RC(upload_desc(c, lv, nseg));
-    GridLevelArgs a{lv.seg, lv.offs, lv.offs + S1, lv.offs + 2 * S1, nseg, chunk[nseg], tile[nseg], act[nseg],
-                    next_epoch(c)};
     const bool exact = exact_order(c);
     {
         Span s(c, F_SWEEP);
@@ -718,12 +760,14 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
         // the permutation), the kick list, first half, kick and closing drift
         // of the level, second half, then back to the entry order.
         int nblk = 0, njobs = 0;
-        RC(upload_kick_list(c, lv, segs, big, &nblk, &njobs));
+        const unsigned char *big_desc = nullptr;
+        DescTotals big_tot{};
+        RC(upload_kick_list(c, lv, segs, big, &nblk, &njobs, &big_desc, &big_tot));
         const KickTile *ktile = reinterpret_cast<const KickTile *>(lv.kick);
         const KickBlock *kblk = reinterpret_cast<const KickBlock *>(lv.kick + (size_t)a.nchunks * sizeof(KickTile));
         const KickJob *kjob = reinterpret_cast<const KickJob *>(lv.kick + (size_t)a.nchunks * sizeof(KickTile) +
                                                                 (size_t)nblk * sizeof(KickBlock));
-        if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
+        if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small, big_desc, &big_tot));
         Level &lv2 = c->levels[k];
         {
             // the kick, then the second drift of the singletons (fused)
@@ -732,7 +776,7 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h)
                                      c->params.G, mixed(c), c->kick_part, c->parent, cnt_of(c, k + 1), c->errf,
                                      c->stats, c->st));
         }
-        if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small));
+        if (any_sub) RC(dispatch_sets(c, k, c->levels[k], H, big, n_pairs, n_small, big_desc, &big_tot));
         Level &lv3 = c->levels[k];
         Span s(c, F_PERMUTE);
         HIPCHK(launch_permute(Wp, W, a, lv3.src, nullptr, nullptr, nullptr, nullptr, 0.0, nullptr, nullptr, nullptr,
