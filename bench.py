@@ -35,10 +35,10 @@ PEAK_FP64_VECTOR = 78.6e12   # MI355X: 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 # WRITE_SIZE x 1.0, the factors from a plain 256 MiB device copy; see
 # profiles/hbm_traffic_plummer16k_salpeter_fp64.md), valid for the kernel
 # sources with this SHA-1; any other source reports null.
-SWEEP_TRAFFIC_BYTES = 11356618
+SWEEP_TRAFFIC_BYTES = 11286717
 SWEEP_TRAFFIC_SOURCES = ("paper_1407_7105_amd/csrc/cc_kernels.hip", "paper_1407_7105_amd/csrc/cc_device.h",
                          "paper_1407_7105_amd/csrc/cc_screen64.h")
-SWEEP_TRAFFIC_SHA1 = "24df941c7056928e8001f067f351c5d86fe808c0"
+SWEEP_TRAFFIC_SHA1 = "791c7299319d7c72a3032b4c96cffdd0f6d1db73"
 
 
 def sweep_traffic():

@@ -58,8 +58,10 @@ struct Level {
     Seg *pairs = nullptr;
     Seg *small[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t *notstar = nullptr;  // cap_seg: epoch of the visit that found the set not to be a star
+    bool star_hint = false;      // the last visit found a star set: test for stars before sweeping
     // Report block, read back with one copy per visit: count[8] ([0] pairs,
-    // [1..4] small bins, [5] big, [7] error bits) followed by the big list.
+    // [1..4] small bins, [5] big, [6] star segments, [7] error bits) followed
+    // by the big list.
     int32_t *rep = nullptr, *h_rep = nullptr;
     int32_t *count = nullptr, *h_count = nullptr;
     Seg *big = nullptr, *h_big = nullptr;
@@ -691,9 +693,16 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h, const 
         a = desc_args(lv.desc, nseg, t, next_epoch(c));
     }
     const bool exact = exact_order(c);
+    // The star test of Sec. 2.3 runs ahead of the sweep only on levels whose
+    // last visit found a star; otherwise the sweep's first tile row takes it.
+    const bool star_pass = lv.star_hint;
+    if (star_pass) {
+        Span s(c, F_SWEEP);
+        HIPCHK(launch_star(W, a, lv.notstar, p, h, screen32(c), c->stats, fam_ptr(c, F_SWEEP), c->st));
+    }
     {
         Span s(c, F_SWEEP);
-        HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, c->stats,
+        HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, star_pass, c->stats,
                             fam_ptr(c, F_SWEEP), c->st));
     }
     {
@@ -725,6 +734,7 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h, const 
     L.labp = exact ? nullptr : lv.labp;
     L.singp = exact ? nullptr : lv.singp;
     L.errf = c->errf;
+    L.notstar = lv.notstar;
     {
         Span s(c, F_PERMUTE);
         // FAST order: the singletons' first drift touches no particle of a
@@ -741,6 +751,7 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h, const 
     const int n_pairs = lv.h_count[0];
     const int n_small[4] = {lv.h_count[1], lv.h_count[2], lv.h_count[3], lv.h_count[4]};
     const int n_big = lv.h_count[5];
+    lv.star_hint = lv.h_count[6] > 0;
     if (n_pairs > lv.cap_pairs || lv.h_count[1] > lv.cap_small || lv.h_count[2] > lv.cap_small ||
         lv.h_count[3] > lv.cap_small || lv.h_count[4] > lv.cap_small || n_big > lv.cap_big)
         return fail(c, CC_ERR_DEVICE, "internal work-list capacity exceeded");
@@ -1191,7 +1202,8 @@ int cc_split_labels(cc_ctx *c, const cc_state *s, int64_t n, double h, int32_t *
     const DevParams p = dev_params(c);
     SoA S = user_soa(s);
     HIPCHK(launch_uf_init(c->parent, cnt_of(c, 0), (int)n, c->st));
-    HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, c->stats, nullptr, c->st));
+    HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, false, c->stats, nullptr,
+                        c->st));
     HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, cnt_of(c, 0), nullptr, nullptr, nullptr, c->stats, c->st));
     if (n_nontrivial_out) {
         // roots carry their component size in cnt (zeroed for every slot by the reset)

@@ -221,13 +221,45 @@ __global__ void k_uf_init(int32_t *parent, int32_t *cnt, int n)
     }
 }
 
+// Star test (Sec. 2.3, the fully connected case) ahead of the sweep: with X
+// the segment's first slot, the segment is one component if tau(X,U) < h for
+// every other U; notstar[s] is set when some U fails.  Run on levels whose
+// previous visit found a star, so that a star costs n-1 pair steps and the
+// sweep skips it.
+template <bool MIXED>
+__global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg,
+                                               const int32_t *__restrict__ chunk_off, int nseg,
+                                               int32_t *__restrict__ notstar, int32_t epoch, DevParams p, double h,
+                                               uint64_t *stats, uint64_t *fam)
+{
+    __shared__ uint64_t sh[4];
+    const int s = find_seg(chunk_off, nseg, blockIdx.x);
+    const Seg g = seg[s];
+    const int local = (blockIdx.x - chunk_off[s]) * TPB + threadIdx.x;
+    const int X = g.start;
+    uint64_t ev = 0;
+    if (local > 0 && local < g.n) {
+        const int u = g.start + local;
+        ev = 1;
+        if (!edge_decide<MIXED>(S.x[X] - S.x[u], S.y[X] - S.y[u], S.z[X] - S.z[u], S.vx[X] - S.vx[u],
+                                S.vy[X] - S.vy[u], S.vz[X] - S.vz[u], S.m[X] + S.m[u], p, screen_params(p, h),
+                                ccs::screen64_params(p.eta, h), h))
+            notstar[s] = epoch;
+    }
+    const uint64_t t = block_sum_u64(ev, sh);
+    if (threadIdx.x == 0) {
+        stat_add(stats, g.cluster, ST_TAU, t);
+        fam_add(fam, 0, t);
+    }
+}
+
 // All-pairs sweep of a segment: for each pair i<j with tau(i,j) < h, merge
-// their sets.  The tiles of the first row also take the star test of Sec. 2.3
-// (the set is fully connected when its first slot X has tau(X,U) < h with
-// every other U): a tile that sees X miss one of its partners marks the
-// segment in notstar (the test only sets the algorithmic work count).  Work
-// is cut into 64x64 tiles (i tile <= j tile), one per wavefront, four per
-// block.  A wavefront stages
+// their sets.  Without a star pass ahead of it, the tiles of the first row
+// take the star test of Sec. 2.3 themselves (the set is fully connected when
+// its first slot X has tau(X,U) < h with every other U): a tile that sees X
+// miss one of its partners marks the segment in notstar.  After a star pass
+// (star_pass), the tiles of a star segment do nothing.  Work is cut into
+// 64x64 tiles (i tile <= j tile), one per wavefront, four per block.  A wavefront stages
 // its j tile in LDS, joins edges in a union-find local to the tile over its
 // 128 particles (64 when i tile = j tile), skipping an edge whose particles
 // already share the global root read at tile start, and finally merges each
@@ -246,7 +278,7 @@ constexpr int ST = 64;  // sweep tile edge (one wavefront)
 template <bool MIXED, int JS>
 __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ seg,
                                                 const int32_t *__restrict__ tile_off, int nseg,
-                                                int32_t *__restrict__ notstar, int32_t epoch,
+                                                int32_t *__restrict__ notstar, int32_t epoch, int star_pass,
                                                 int32_t *__restrict__ parent, DevParams p, double h,
                                                 uint64_t *stats, uint64_t *fam)
 {
@@ -262,8 +294,11 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
     const int tile = blockIdx.x * TPW + ts;
     const int total = tile_off[nseg];
     int s = 0, ti = 0, tj = 0, T = 0;
-    const bool active = tile < total;
-    if (active) s = find_seg(tile_off, nseg, tile);
+    bool active = tile < total;
+    if (active) {
+        s = find_seg(tile_off, nseg, tile);
+        active = !star_pass || notstar[s] == epoch;
+    }
     Seg g{0, 0, 0, 0};
     if (active) {
         g = seg[s];
@@ -387,7 +422,7 @@ __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, cons
     int32_t l = -1;
     if (valid) {
         const int u = g.start + local;
-        l = gfind(parent, u);
+        l = ns ? gfind(parent, u) : g.start;
         label[u] = l;
         if (keys) {
             const int k = act_off[s] + local;
@@ -426,6 +461,7 @@ struct Lists {
     int32_t *labp;       // optional: label of the particle now at each slot
     uint8_t *singp;      // optional: singleton flag of the particle now at each slot
     const int32_t *errf; // error bits, copied to count[7] for the host's one read-back
+    const int32_t *notstar;  // the level's not-a-star flags: star segments are counted in count[6]
 };
 
 // Forward permutation of a level between the two working buffers: the k-th
@@ -445,7 +481,7 @@ __global__ __launch_bounds__(TPB) void k_permute(SoA from, SoA to, const Seg *__
                                                   const int32_t *__restrict__ cnt, uint8_t *__restrict__ sing, Lists L,
                                                   int with_lists, double drift_hh, int32_t *__restrict__ parent,
                                                   int32_t *__restrict__ cnt_next, uint64_t *kick_fam, int count_kick,
-                                                  uint64_t *stats)
+                                                  int32_t epoch, uint64_t *stats)
 {
     __shared__ uint64_t sh[4];
     const int s = find_seg(chunk_off, nseg, blockIdx.x);
@@ -484,6 +520,7 @@ __global__ __launch_bounds__(TPB) void k_permute(SoA from, SoA to, const Seg *__
             if (sing) sing[u] = single ? 1 : 0;
             if (with_lists) {
                 if (k == 0) L.count[7] = __hip_atomic_load(L.errf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (local == 0 && L.notstar[s] != epoch) atomicAdd(&L.count[6], 1);  // a star segment
                 if (count_kick && local == 0) {
                     // the tiled kick's pairs: all of the segment's ...
                     const uint64_t all = (uint64_t)g.n * (uint64_t)(g.n - 1) / 2;
@@ -1576,8 +1613,20 @@ hipError_t launch_uf_init(int32_t *parent, int32_t *cnt, int n, hipStream_t st)
     return hipGetLastError();
 }
 
+hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, DevParams p, double h, bool mixed,
+                       uint64_t *stats, uint64_t *fam, hipStream_t st)
+{
+    if (mixed)
+        hipLaunchKernelGGL(k_star<true>, dim3(a.nchunks), dim3(TPB), 0, st, S, a.seg, a.chunk_off, a.nseg, notstar,
+                           a.epoch, p, h, stats, fam);
+    else
+        hipLaunchKernelGGL(k_star<false>, dim3(a.nchunks), dim3(TPB), 0, st, S, a.seg, a.chunk_off, a.nseg, notstar,
+                           a.epoch, p, h, stats, fam);
+    return hipGetLastError();
+}
+
 hipError_t launch_sweep(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, DevParams p, double h,
-                        bool mixed, int split_tiles, uint64_t *stats, uint64_t *fam, hipStream_t st)
+                        bool mixed, int split_tiles, bool star_pass, uint64_t *stats, uint64_t *fam, hipStream_t st)
 {
     if (a.ntiles == 0) return hipSuccess;
     const int js = a.ntiles <= split_tiles ? 4 : 1;
@@ -1585,7 +1634,7 @@ hipError_t launch_sweep(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t
     const int nb = (a.ntiles + tpb - 1) / tpb;
 #define CC_SWEEP(M, J)                                                                                          \
     hipLaunchKernelGGL((k_sweep<M, J>), dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar, a.epoch, \
-                       parent, p, h, stats, fam)
+                       star_pass ? 1 : 0, parent, p, h, stats, fam)
     if (mixed) {
         if (js == 4) CC_SWEEP(true, 4);
         else if (js == 2) CC_SWEEP(true, 2);
@@ -1654,9 +1703,11 @@ hipError_t launch_permute(SoA from, SoA to, const GridLevelArgs &a, const uint32
         L.labp = lists->labp;
         L.singp = lists->singp;
         L.errf = lists->errf;
+        L.notstar = lists->notstar;
     }
     hipLaunchKernelGGL(k_permute, dim3(a.nchunks), dim3(TPB), 0, st, from, to, a.seg, a.chunk_off, a.act_off, a.nseg,
-                       src, lab, cnt, sing, L, with, drift_hh, parent, cnt_next, kick_fam, count_kick ? 1 : 0, stats);
+                       src, lab, cnt, sing, L, with, drift_hh, parent, cnt_next, kick_fam, count_kick ? 1 : 0,
+                       a.epoch, stats);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ struct ListArgs {
     int32_t *labp;   // optional permuted-order labels
     uint8_t *singp;  // optional permuted-order singleton flags
     const int32_t *errf;  // error bits, snapshot into count[7]
+    const int32_t *notstar;  // not-a-star flags: star segments are counted into count[6]
 };
 
 struct SmallArgs {
@@ -54,7 +55,11 @@ hipError_t launch_uf_init(int32_t *parent, int32_t *cnt, int n, hipStream_t st);
 // the kernels' edge test); split_tiles: launches of at most this many tiles
 // take one block per tile
 hipError_t launch_sweep(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, DevParams p, double h,
-                        bool screen32, int split_tiles, uint64_t *stats, uint64_t *fam, hipStream_t st);
+                        bool screen32, int split_tiles, bool star_pass, uint64_t *stats, uint64_t *fam, hipStream_t st);
+// star test of every segment from its first slot (sets notstar for the
+// segments that are not fully connected)
+hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, DevParams p, double h, bool screen32,
+                       uint64_t *stats, uint64_t *fam, hipStream_t st);
 // labels and component sizes; with keys/vals the sort keys of the active
 // particles, with count the work-list counters cleared
 hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,
