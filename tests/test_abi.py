@@ -40,3 +40,16 @@ def test_binding_rejects_missing_library(tmp_path, monkeypatch):
     monkeypatch.setattr(cc, "_lib", None)
     with pytest.raises(ImportError):
         cc.load_library()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with status 2 and says
+    so before touching any device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
