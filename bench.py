@@ -1,23 +1,39 @@
-"""Benchmark: one CC global step of the 16384-body Salpeter Plummer workload.
+"""Benchmark: CC global steps of the 262 144-body Plummer workload with hard
+binaries (Salpeter masses 0.1-100, 10% binaries with a log-uniform in
+[1e-5, 1e-3]), FP64, on one GPU.
 
-`python bench.py [--steps K] [--warmup W] [--precision fp64|mixed]` runs W
-untimed and K timed steps on one GPU and prints one JSON line.  A step is one
-global step evolve_cc(all, dt=1/64) (split, recursion into every component,
-drift/kick/drift), started each time from the same initial conditions, which
-are already resident in HBM.  `value` is algorithmic pair interactions per
-second: the pair time steps the splits need (n-1 for a fully connected set,
-n(n-1)/2 otherwise) plus the pairs kicked, divided by the wall time per step.
+`python bench.py [--steps K] [--warmup W]` integrates W untimed and then K
+timed global steps of evolve_cc(all, dt0) (split, recursion into every
+component, drift/kick/drift) from the workload's initial conditions, which
+are resident in HBM before the timed region starts.  The global pivot step is
+dt0 = 1/512: the top of the power-of-two hierarchy is a free parameter of the
+method, and with it one step of this workload is a bounded unit of work
+(about 1/8 of a step at 1/64, the same levels below).  `value` is algorithmic
+pair interactions per second: the pair time steps the splits need (n-1 for a
+fully connected set, n(n-1)/2 otherwise) plus the pairs kicked (label_i !=
+label_j), over the wall time of the K steps.
 
-The line also carries an eta scan (`eta_scan`, skipped with --no-eta-scan):
-the same workload integrated for four global steps with FP64 and with mixed
-precision at several eta, its energy error |dE/E| and wall seconds per N-body
-time unit, and for each precision the largest eta that keeps |dE/E| <= 1e-6.
+Beside the headline the line carries
+  - `roofline`: the sweep (the kernel family with most of the arithmetic),
+    from HIP events around each of its launches on the stream it runs on,
+    recorded during the timed steps; `roofline_kick` the same for the kick;
+  - `conservation`: |dE/E|, |dP| and |dL| over the integrated time;
+  - `mixed_force_error`: rms and max relative error of the mixed-precision
+    kick against the FP64 kick on every particle of the workload;
+  - `eta_scan`: FP64 and mixed precision at several eta from the same initial
+    conditions, their |dE/E| and wall seconds per N-body time, and the speed
+    ratio at equal |dE/E| <= 1e-6;
+  - `secondary`: the 16 384-body Salpeter Plummer workload, one global step
+    at dt0 = 1/64 restarted from its initial conditions;
+  - `cpu_baseline`: the FP64 CPU oracle on a bounded sample of the same state,
+    on one host thread and on all host cores of this process.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -31,70 +47,198 @@ FLOP_TAU = 48      # FP64 operations of one pair time step, eq. 19 (div and sqrt
 FLOP_KICK = 26     # FP64 operations of one symmetric pair kick, eqs. 8-9
 PEAK_FP64_VECTOR = 78.6e12   # MI355X: 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 
-# HBM bytes per sweep launch on this workload (rocprofv3 FETCH_SIZE x 2.0 +
-# WRITE_SIZE x 1.0, the factors from a plain 256 MiB device copy; see
-# profiles/hbm_traffic_plummer16k_salpeter_fp64.md), valid for the kernel
-# sources with this SHA-1; any other source reports null.
-SWEEP_TRAFFIC_BYTES = 11286717
+HEADLINE = 5       # workload index in synth.WORKLOADS
+DT0 = 1.0 / 512
+
+# HBM bytes per sweep launch on this workload and step (rocprofv3 FETCH_SIZE
+# x 2.0 + WRITE_SIZE x 1.0, the factors from a plain 256 MiB device copy; see
+# profiles/hbm_traffic_plummer262k_salpeter_bin10_fp64.md), valid for the
+# kernel sources with this SHA-1 only: any other source reports null.
+SWEEP_TRAFFIC_BYTES = None
 SWEEP_TRAFFIC_SOURCES = ("paper_1407_7105_amd/csrc/cc_kernels.hip", "paper_1407_7105_amd/csrc/cc_device.h",
                          "paper_1407_7105_amd/csrc/cc_screen64.h")
-SWEEP_TRAFFIC_SHA1 = "791c7299319d7c72a3032b4c96cffdd0f6d1db73"
+SWEEP_TRAFFIC_SHA1 = None
 
 
-def sweep_traffic():
+def sources_sha1():
     import hashlib
     h = hashlib.sha1()
     for f in SWEEP_TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return SWEEP_TRAFFIC_BYTES if h.hexdigest() == SWEEP_TRAFFIC_SHA1 else None
+    return h.hexdigest()
 
 
-def cpu_baseline(p, dt, eta):
-    """The FP64 oracle on a bounded sample of the same workload (one host
-    thread): its breadth-first split of all particles at the pivot steps
-    dt, dt/2, ..., dt/128 (the levels where the large component lives) and
-    four kicks of every pair (the kick sweep at its full size)."""
+def sweep_traffic():
+    if SWEEP_TRAFFIC_BYTES is None:
+        return None
+    return SWEEP_TRAFFIC_BYTES if sources_sha1() == SWEEP_TRAFFIC_SHA1 else None
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def host_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))   # a GPU's share of the host
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline (the only part of this file that runs the oracle)
+# ---------------------------------------------------------------------------
+_SAMPLE = {}
+
+
+def _oracle_share(task):
+    """One share of the baseline sample: oracle BFS splits of a random
+    subsample of the state at the pivot steps dt0/2^k, and the oracle's pair
+    kick sums of a slice of sampled particles against all n."""
     import oracle
-    q = p.copy()
+    p, dt0, eta = _SAMPLE["p"], _SAMPLE["dt0"], _SAMPLE["eta"]
+    seed, nsub, levels, idx = task
+    from synth import Particles
     par = oracle.Params(eta=eta)
-    evals = pairs = 0
-    t0 = time.perf_counter()
-    for k in range(8):
-        _, _, e = oracle.split_labels(q, dt / 2 ** k, par)
+    rng = np.random.default_rng(seed)
+    sub = np.sort(rng.choice(p.n, nsub, replace=False))
+    q = Particles(*(np.ascontiguousarray(a[sub]) for a in p.arrays()))   # the subsample, contiguous
+    evals = 0
+    for k in levels:
+        _, e = oracle.split_bfs(q, dt0 / 2 ** k, p=par)
         evals += e
-    for _ in range(4):
-        pairs += oracle.kick(q, dt, p=par)
+    pairs = 0
+    if len(idx):
+        oracle.accel(p, np.asarray(idx, np.int64), par)
+        pairs = len(idx) * (p.n - 1)
+    return evals, pairs
+
+
+def cpu_baseline(p, dt0, eta, seed=7105):
+    """The oracle, as it stands, on a bounded sample of the headline state:
+    BFS splits (Sec. 2.3) of 14 000-particle subsamples at dt0/2^k, k = 0..5,
+    and all-partner kick sums (eqs. 8-9) of 1024 sampled particles.  Timed on
+    one host thread, then the same amount of work split over the host cores
+    (one process per core)."""
+    import multiprocessing as mp
+
+    _SAMPLE.update(p=p, dt0=dt0, eta=eta)
+    rng = np.random.default_rng(seed)
+    acc_idx = rng.choice(p.n, 1024, replace=False)
+    nsub = 14000
+    t0 = time.perf_counter()
+    e1, k1 = _oracle_share((seed, nsub, list(range(6)), acc_idx))
     t1 = time.perf_counter()
-    return {"value": (evals + pairs) / (t1 - t0), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle on the same 16384-body state: splits at dt/2^k, k=0..7 ({evals} tau "
-                      f"evaluations) and 4 all-pair kicks ({pairs} pairs); {t1 - t0:.1f} s on one host thread"}
+    single = (e1 + k1) / (t1 - t0)
+    out = {"value": single, "unit": "pairs/s", "cores": 1, "kind": "oracle", "cpu": cpu_model(),
+           "sample": f"oracle on the headline state (n = {p.n}): BFS splits of a {nsub}-particle random subsample at "
+                     f"dt0/2^k, k = 0..5 ({e1} tau evaluations), and all-partner kick sums of 1024 sampled "
+                     f"particles ({k1} pairs); {t1 - t0:.1f} s on one host thread"}
+    nproc = host_threads()
+    if nproc > 1:
+        # about the same total work in nproc equal shares: every process splits
+        # a subsample of nsub / sqrt(nproc) particles at the six levels (a
+        # split costs the square of the set size) and takes 1/nproc of the
+        # sampled kick rows
+        nsub_w = int(round(nsub / np.sqrt(nproc)))
+        tasks = [(seed + 1 + w, nsub_w, list(range(6)), acc_idx[w::nproc]) for w in range(nproc)]
+        ctx = mp.get_context("fork")   # no GPU state exists yet in this process
+        t0 = time.perf_counter()
+        with ctx.Pool(nproc) as pool:
+            res = pool.map(_oracle_share, tasks)
+        t1 = time.perf_counter()
+        e = sum(r[0] for r in res)
+        k = sum(r[1] for r in res)
+        out["all_cores"] = {"value": (e + k) / (t1 - t0), "unit": "pairs/s", "cores": nproc,
+                            "sample": f"{nproc} processes, each splitting a {nsub_w}-particle subsample at the "
+                                      f"same six levels and taking 1/{nproc} of the kick rows ({e} tau "
+                                      f"evaluations, {k} pairs); {t1 - t0:.1f} s"}
+    return out
 
 
-def eta_scan(p, wl, dev, small_max, etas=(0.01, 0.03, 0.1, 0.3), steps=4, bound=1e-6):
-    """FP64 against mixed precision at equal energy error: each precision is
-    run at every eta for `steps` global steps from the same initial conditions;
-    |dE/E| comes from the library's compensated diagnostics (eqs. 1-3)."""
+# ---------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------
+def roofline_of(fam, name, flop_per_tau, flop_per_kick, traffic=None):
+    v = fam.get(name)
+    if not v or not v["launches"] or v["ms"] <= 0:
+        return None
+    flops = flop_per_tau * v["tau_pairs"] + flop_per_kick * v["kick_pairs"]
+    achieved = flops / (v["ms"] * 1e-3) / 1e12
+    return {"kernel": name, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64_VECTOR / 1e12), "traffic": traffic,
+            "traffic_unit": "bytes per launch", "launches": v["launches"], "avg_launch_ms": v["ms"] / v["launches"],
+            "flop_per_unit": {"tau_pair": flop_per_tau, "kick_pair": flop_per_kick},
+            "units": {"tau_pairs": v["tau_pairs"], "kick_pairs": v["kick_pairs"]}}
+
+
+def conservation(d0, d1, p):
+    ms = p.m
+    pscale = float(np.sum(ms * np.sqrt(p.vx ** 2 + p.vy ** 2 + p.vz ** 2)))
+    r = np.stack([p.x, p.y, p.z], 1)
+    v = np.stack([p.vx, p.vy, p.vz], 1)
+    lscale = float(np.sum(ms * np.linalg.norm(np.cross(r, v), axis=1)))
+    dP = float(np.linalg.norm(np.asarray(d1["P"]) - np.asarray(d0["P"])))
+    dL = float(np.linalg.norm(np.asarray(d1["L"]) - np.asarray(d0["L"])))
+    return {"dE_over_E": abs((d1["energy"] - d0["energy"]) / d0["energy"]), "dP": dP, "dP_rel": dP / pscale,
+            "dL": dL, "dL_rel": dL / lscale, "E0": d0["energy"], "E1": d1["energy"]}
+
+
+def mixed_force_error(p, wl, dev):
+    """rms and max over all particles of |a_mixed - a_fp64| / |a_fp64|, from
+    the library's kick (velocities start at zero, h = 1) in both precisions."""
     import torch
 
     from paper_1407_7105_amd import CC_FP64, CC_MIXED, Context, State
-    dt = wl["dt"]
+    acc = {}
+    for name, prec in (("fp64", CC_FP64), ("mixed", CC_MIXED)):
+        ctx = Context(device=0, eta=wl["eta"], eps2=wl["eps2"], precision=prec)
+        s = State.from_numpy(p, device=dev)
+        for f in ("vx", "vy", "vz"):
+            getattr(s, f).zero_()
+        ctx.kick(s, 1.0)
+        torch.cuda.synchronize()
+        acc[name] = torch.stack([s.vx, s.vy, s.vz], 1)
+        ctx.close()
+    num = torch.linalg.norm(acc["mixed"] - acc["fp64"], dim=1)
+    den = torch.linalg.norm(acc["fp64"], dim=1)
+    rel = (num / den).cpu().numpy()
+    return {"rms": float(np.sqrt(np.mean(rel ** 2))), "max": float(rel.max()), "median": float(np.median(rel)),
+            "particles": int(rel.size), "reference": "the library's FP64 kick (bit-identical to the oracle's sums)"}
+
+
+def eta_scan(p, wl, dev, dt0, etas=(0.01, 0.03, 0.1), steps=2, bound=1e-6):
+    """FP64 against mixed precision at equal energy error: each precision runs
+    `steps` global steps at every eta from the same initial conditions;
+    |dE/E| from the library's compensated diagnostics (eqs. 1-3)."""
+    import torch
+
+    from paper_1407_7105_amd import CC_FP64, CC_MIXED, Context, State
     rows = []
     for name, prec in (("fp64", CC_FP64), ("mixed", CC_MIXED)):
         for eta in etas:
-            ctx = Context(device=0, eta=eta, eps2=wl["eps2"], precision=prec, small_max=small_max)
+            ctx = Context(device=0, eta=eta, eps2=wl["eps2"], precision=prec)
             s = State.from_numpy(p, device=dev)
             e0 = ctx.diagnostics(s)["energy"]
-            ctx.evolve(s, dt, dt)  # warm-up of this context's buffers, then the timed run from the start
-            s = State.from_numpy(p, device=dev)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ctx.evolve(s, dt, steps * dt)
+            st = ctx.evolve(s, dt0, steps * dt0)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             e1 = ctx.diagnostics(s)["energy"]
             rows.append({"precision": name, "eta": eta, "dE_over_E": abs((e1 - e0) / e0),
-                         "wall_s_per_nbody_time": wall / (steps * dt)})
+                         "wall_s_per_nbody_time": wall / (steps * dt0), "kick_pairs": st["kick_pairs"],
+                         "tau_pairs_alg": st["tau_pairs_alg"]})
+            ctx.close()
             print(f"# eta scan {name} eta={eta}: |dE/E|={rows[-1]['dE_over_E']:.3e} "
                   f"{rows[-1]['wall_s_per_nbody_time']:.3f} s per N-body time", file=sys.stderr, flush=True)
     chosen = {}
@@ -104,8 +248,40 @@ def eta_scan(p, wl, dev, small_max, etas=(0.01, 0.03, 0.1, 0.3), steps=4, bound=
     ratio = None
     if chosen["fp64"] and chosen["mixed"]:
         ratio = chosen["fp64"]["wall_s_per_nbody_time"] / chosen["mixed"]["wall_s_per_nbody_time"]
-    return {"t": steps * dt, "bound": bound, "rows": rows, "chosen": chosen,
+    return {"t": steps * dt0, "dt0": dt0, "bound": bound, "rows": rows, "chosen": chosen,
             "mixed_speedup_at_equal_dE": ratio}
+
+
+def secondary(dev, steps=3):
+    """The 16 384-body Salpeter Plummer workload: one global step at dt0 = 1/64,
+    restarted from its initial conditions each time."""
+    import torch
+
+    import synth
+    from paper_1407_7105_amd import Context, State
+    wl = synth.WORKLOADS[2]
+    p = synth.workload(2)
+    ic = State.from_numpy(p, device=dev)
+    s = ic.copy()
+    ctx = Context(device=0, eta=wl["eta"], eps2=wl["eps2"])
+
+    def step():
+        for f in State.FIELDS:
+            getattr(s, f).copy_(getattr(ic, f))
+        return ctx.evolve(s, wl["dt"], wl["dt"])
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    work = 0
+    for _ in range(steps):
+        st = step()
+        work += st["tau_pairs_alg"] + st["kick_pairs"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.close()
+    return {"workload": wl["name"], "n": p.n, "dt0": wl["dt"], "steps": steps,
+            "ms_per_step": (t1 - t0) * 1e3 / steps, "value": work / (t1 - t0), "unit": "pairs/s"}
 
 
 def main():
@@ -114,107 +290,113 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--dt0", type=float, default=DT0, help="global pivot step (power of two)")
     ap.add_argument("--small-max", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--no-eta-scan", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-force-error", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the launch shapes on this workload first (the library defaults are the tuner's "
-                         "choice for it)")
+                         "choice on the 16 384-body workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md for how the "
               "sweep would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    import synth
+    wl = synth.WORKLOADS[HEADLINE]
+    eta = wl["eta"]
+    dt0 = args.dt0
+    t_gen = time.perf_counter()
+    p = synth.workload(HEADLINE)
+    print(f"# workload {wl['name']}: n = {p.n}, generated in {time.perf_counter() - t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+
+    base = None
+    if not args.no_cpu_baseline:
+        # before anything touches the GPU (the all-cores leg forks workers)
+        base = cpu_baseline(p, dt0, eta)
+        print(f"# cpu baseline: {base['value']:.3e} pairs/s on one thread"
+              + (f", {base['all_cores']['value']:.3e} on {base['all_cores']['cores']}" if "all_cores" in base else ""),
+              file=sys.stderr, flush=True)
+
     import torch
 
-    import synth
     from paper_1407_7105_amd import CC_FP64, CC_MIXED, Context, State
 
-    wl = synth.WORKLOADS[2]
-    dt, eta = wl["dt"], wl["eta"]
-    p = synth.workload(2)
     dev = torch.device("cuda:0")
-    ic = State.from_numpy(p, device=dev)
-    s = ic.copy()
     prec = CC_FP64 if args.precision == "fp64" else CC_MIXED
     ctx = Context(device=0, eta=eta, eps2=wl["eps2"], precision=prec, small_max=args.small_max)
-
-    def step():
-        for f in State.FIELDS:
-            getattr(s, f).copy_(getattr(ic, f))
-        return ctx.evolve(s, dt, dt)
+    s = State.from_numpy(p, device=dev)
+    d0 = ctx.diagnostics(s)
 
     tune = None
     if args.autotune:
-        # launch shapes (on-chip size limit, sweep tiles per workgroup) from
-        # the library's autotuner, on this workload, before anything is timed
-        tune = ctx.autotune(ic, dt)
+        tune = ctx.autotune(s, dt0)
         print(f"# autotune: {tune}", file=sys.stderr, flush=True)
 
     for i in range(args.warmup):
         t = time.perf_counter()
-        step()
+        ctx.evolve(s, dt0, dt0)
+        torch.cuda.synchronize()
         print(f"# warmup step {i}: {time.perf_counter() - t:.3f} s", file=sys.stderr, flush=True)
+
+    # timed steps, with every launch bracketed by HIP events on its own stream
+    ctx.timing(True)
     torch.cuda.synchronize()
-    work = 0
+    work = tau_alg = kick = 0
+    totals = {}
     t0 = time.perf_counter()
-    stats = None
-    for _ in range(args.steps):
-        stats = step()
-        work += stats["tau_pairs_alg"] + stats["kick_pairs"]
+    for i in range(args.steps):
+        st = ctx.evolve(s, dt0, dt0)
+        work += st["tau_pairs_alg"] + st["kick_pairs"]
+        for k, v in st.items():
+            if k not in ("t_reached", "max_depth_seen"):
+                totals[k] = totals.get(k, 0) + v
+        totals["max_depth_seen"] = max(totals.get("max_depth_seen", 0), st["max_depth_seen"])
+        print(f"# timed step {i}: {time.perf_counter() - t0:.3f} s cumulative", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    fam = ctx.timing_report()
+    ctx.timing(False)
     ms = (t1 - t0) * 1e3 / args.steps
-    print(f"# timed: {args.steps} steps, {ms:.2f} ms/step", file=sys.stderr, flush=True)
     value = work / (t1 - t0)
+    print(f"# timed: {args.steps} steps, {ms:.2f} ms/step, {value:.3e} pairs/s", file=sys.stderr, flush=True)
 
-    roof = None
-    fam = None
-    if not args.no_roofline:
-        # same steps again with every launch bracketed by HIP events on the library's stream
-        ctx.timing(True)
-        for _ in range(args.steps):
-            step()
-        fam = ctx.timing_report()
-        ctx.timing(False)
-        busy = {k: v for k, v in fam.items() if v["launches"]}
+    d1 = ctx.diagnostics(s)
+    cons = conservation(d0, d1, p)
+    cons["t"] = (args.warmup + args.steps) * dt0
 
-        def flops_of(v):
-            return FLOP_TAU * v["tau_pairs"] + FLOP_KICK * v["kick_pairs"]
+    roof = roofline_of(fam, "sweep", FLOP_TAU, 0, sweep_traffic())
+    roof_kick = roofline_of(fam, "kick", 0, FLOP_KICK)
+    ctx.close()
 
-        # the dominant kernel is the family doing most of the step's arithmetic
-        # (the sweep); the on-chip components' launches run beside it on a
-        # second stream, so their event time overlaps it and is latency, not work
-        dom = max(busy, key=lambda k: flops_of(busy[k]))
-        d = busy[dom]
-        flops = flops_of(d)
-        achieved = flops / (d["ms"] * 1e-3) / 1e12 if d["ms"] > 0 else 0.0
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / (PEAK_FP64_VECTOR / 1e12),
-                "traffic": sweep_traffic() if dom == "sweep" else None, "traffic_unit": "bytes per launch",
-                "avg_launch_ms": d["ms"] / d["launches"], "launches_per_step": d["launches"] / args.steps}
-
-    scan = None if args.no_eta_scan else eta_scan(p, wl, dev, args.small_max)
+    ferr = None if args.no_force_error else mixed_force_error(p, wl, dev)
+    scan = None if args.no_eta_scan else eta_scan(p, wl, dev, dt0)
+    sec = None if args.no_secondary else secondary(dev)
 
     out = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if prec == CC_FP64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "plummer16k_salpeter", "n": p.n, "imf": "salpeter 0.1-100",
-                   "eta": eta, "eps": 0.0, "dt": dt, "step": "one CC global step",
-                   "launch_shapes": tune},
-        "wall_s_per_nbody_time": (ms / 1e3) / dt,
-        "stats_per_step": stats,
+        "config": {"workload": wl["name"], "n": p.n, "imf": "salpeter 0.1-100", "binaries": "10%, a in [1e-5, 1e-3]",
+                   "eta": eta, "eps": 0.0, "dt0": dt0, "step": "one CC global step (continuing integration)",
+                   "kick_order": "fast", "launch_shapes": tune},
+        "wall_s_per_nbody_time": (ms / 1e3) / dt0,
+        "stats_timed_steps": totals,
         "roofline": roof,
-        "kernel_ms_per_step": None if fam is None else
-        {k: round(v["ms"] / args.steps, 4) for k, v in fam.items() if v["launches"]},
+        "roofline_kick": roof_kick,
+        "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in fam.items() if v["launches"]},
+        "conservation": cons,
+        "mixed_force_error": ferr,
         "eta_scan": scan,
+        "secondary": sec,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, dt, eta)
+    if base is not None:
+        out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
 
 

@@ -43,8 +43,10 @@ typedef enum {
 
 typedef enum {
     CC_FP64 = 0,            /* plain path: every sweep in FP64 */
-    CC_MIXED = 1            /* FP32 sweeps on offsets from the component centre, FP64
-                               state, drift, close pairs and connectivity decisions */
+    CC_MIXED = 1            /* FP32 pair forces on FP64 coordinate differences, Kahan-
+                               compensated per tile and summed in FP64 across tiles, and
+                               the FP32 screen in front of the FP64 one; FP64 state,
+                               drift and every connectivity decision */
 } cc_precision;
 
 typedef enum {
@@ -135,9 +137,12 @@ int cc_split_labels(cc_ctx *ctx, const cc_state *s, int64_t n, double h,
 /* Kick operator K_h (eqs. 8-9) for every unordered pair i<j with
  * label[i] != label[j] (label: device int32[n], or NULL for every pair):
  *   v_i += h * sum_j G m_j (q_j - q_i) / (|q_j - q_i|^2 + eps^2)^(3/2),
- * each particle's sum taken over j in ascending index order.  Fails with
- * CC_ERR_NONFINITE (state untouched) if a kicked pair has r^2 + eps^2 == 0;
- * the call then syncs. Otherwise asynchronous. */
+ * each particle's sum taken over j in ascending index order.  With
+ * params.precision == CC_MIXED the pair forces are FP32 on FP64 coordinate
+ * differences, Kahan-compensated over each 256-partner tile and summed in
+ * FP64 across tiles.  Fails with CC_ERR_NONFINITE (state untouched) if a
+ * kicked pair has r^2 + eps^2 == 0; the call syncs (it reads back the error
+ * flag before it applies the kick). */
 int cc_kick(cc_ctx *ctx, cc_state *s, int64_t n, const int32_t *label, double h, void *stream);
 
 /* Drift operator D_h (eq. 6): q_i += h v_i for every i with mask[i] != 0

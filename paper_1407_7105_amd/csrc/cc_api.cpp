@@ -1230,7 +1230,7 @@ int cc_kick(cc_ctx *c, cc_state *s, int64_t n, const int32_t *label, double h, v
     SoA S = user_soa(s);
     double *ax = c->kick_acc, *ay = ax + c->cap, *az = ay + c->cap;
     HIPCHK(launch_fill_i32(c->errf, 1, 0, c->st));
-    HIPCHK(launch_kick_all(S, (int)n, label, c->params.eps2, c->params.G, ax, ay, az, c->errf, c->st));
+    HIPCHK(launch_kick_all(S, (int)n, label, c->params.eps2, c->params.G, mixed(c), ax, ay, az, c->errf, c->st));
     RC(sync_read_err(c));
     if (*c->h_err) return err_code(c, *c->h_err);
     HIPCHK(launch_apply_kick(S, (int)n, ax, ay, az, h, c->st));

@@ -67,11 +67,22 @@ enum StatIdx {
 enum ErrBits { EB_DEPTH = 1, EB_NONFINITE = 2, EB_MASS = 4, EB_CAPACITY = 8, EB_BUDGET = 16 };
 
 // Work budgets that turn a runaway recursion (or a corrupted structure) into
-// an error instead of an endless kernel: leaves of one two-particle walk,
-// level visits of one on-chip item, steps of one union-find walk.
-constexpr uint64_t PAIR_LEAF_BUDGET = 1ull << 28;
-constexpr uint64_t ITEM_VISIT_BUDGET = 1ull << 24;
-constexpr int FIND_BUDGET = 1 << 22;
+// an error within seconds instead of an endless kernel.
+//   - leaves of one two-particle walk in one launch: the hardest binaries of
+//     the 262 144-body workload (a = 1e-5, e up to 0.999, the heaviest masses)
+//     need about 2^22 leaves over h = 1/128 (some 1800 orbits of about 2000
+//     leaves at eta = 0.01); 2^24 leaves take about 10 s on one lane;
+//   - level visits of one on-chip item in one launch (a visit is one split or
+//     one kick of a level in LDS, a few to tens of microseconds);
+//   - steps of one union-find walk: links point to smaller slots only, so a
+//     walk ends within the set size (at most 1024 in LDS; the global sets of
+//     the workloads hold at most 2^18 slots and path halving keeps the walks
+//     far shorter); retries of one union, each lost to another thread's link.
+constexpr uint64_t PAIR_LEAF_BUDGET = 1ull << 24;
+constexpr uint64_t ITEM_VISIT_BUDGET = 1ull << 20;
+constexpr int FIND_BUDGET = 1 << 20;
+constexpr int UNITE_RETRIES = 1 << 16;
+constexpr int LDS_FIND_BUDGET = 1 << 11;
 
 // The global union-find keeps one parent entry per 128-byte line: its
 // coherent loads, path-halving stores and compare-and-swaps come from every

@@ -98,7 +98,7 @@ __device__ __forceinline__ int32_t gfind(int32_t *par, int32_t a)
 
 __device__ __forceinline__ int32_t gunite(int32_t *par, int32_t a, int32_t b)
 {
-    for (int it = 0; it < FIND_BUDGET; ++it) {
+    for (int it = 0; it < UNITE_RETRIES; ++it) {
         a = gfind(par, a);
         b = gfind(par, b);
         if (a == b) return a;
@@ -129,7 +129,7 @@ __device__ __forceinline__ void lstore(int32_t *p, int32_t v)
 // which keeps the structure valid under concurrent hooking.
 __device__ __forceinline__ int32_t lfind(int32_t *par, int32_t a)
 {
-    for (int it = 0; it < FIND_BUDGET; ++it) {
+    for (int it = 0; it < LDS_FIND_BUDGET; ++it) {
         const int32_t q = lload(&par[a]);
         if (q == a) return a;
         const int32_t g = lload(&par[q]);
@@ -142,7 +142,7 @@ __device__ __forceinline__ int32_t lfind(int32_t *par, int32_t a)
 // Joins the sets of a and b; returns the root of the joined set (as seen now).
 __device__ __forceinline__ int32_t lunite(int32_t *par, int32_t a, int32_t b)
 {
-    for (int it = 0; it < FIND_BUDGET; ++it) {
+    for (int it = 0; it < LDS_FIND_BUDGET; ++it) {
         a = lfind(par, a);
         b = lfind(par, b);
         if (a == b) return a;
@@ -346,24 +346,36 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
         const double vxi = S.vx[i], vyi = S.vy[i], vzi = S.vz[i], mi = S.m[i];
         const ScreenParams q = screen_params(p, h);
         const ccs::Screen64 s64 = ccs::screen64_params(p.eta, h);
+        const ccs::Far64 f64 = ccs::far64_params(p.eta, h);
         // Decide every pair first (one bit per partner: edge, or left to the
-        // literal formula), with a loop that is uniform across the
-        // wavefront; then resolve the undecided pairs and link the edges.
-        uint64_t emask = 0, umask = 0;
-        // two partners per trip: independent chains hide FP64 latency
-#pragma unroll 2
+        // literal formula), then resolve the undecided pairs and link the
+        // edges.  Stage one, uniform across the wavefront: the far-pair test
+        // on r^2, |u|^2 and mu, which settles most pairs of the deep levels.
+        uint64_t smask = 0;
+#pragma unroll 4
         for (int jj = 0; jj < jnw; ++jj) {
+            const double dx = xi - jx[w][jj], dy = yi - jy[w][jj], dz = zi - jz[w][jj];
+            const double dvx = vxi - jvx[w][jj], dvy = vyi - jvy[w][jj], dvz = vzi - jvz[w][jj];
+            const double r2 = ((dx * dx + dy * dy) + dz * dz) + p.eps2;
+            const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
+            const double mu = p.G * (mi + jm[w][jj]);
+            smask |= ccs::far64(r2, v2, mu, f64) ? 0ull : (1ull << jj);
+        }
+        // partners of this lane: j > i on the diagonal tile, all j otherwise
+        const int sh = lane + 1 - j0w;  // first partner bit with j > i
+        const uint64_t keep = !ivalid ? 0ull : (!diag || sh <= 0) ? ~0ull : (sh >= 64) ? 0ull : (~0ull << sh);
+        smask &= keep;
+        // Stage two, each lane over its own open pairs: the certified screen.
+        uint64_t emask = 0, umask = 0;
+        while (smask) {
+            const int jj = __builtin_ctzll(smask);
+            smask &= smask - 1;
             const int d = edge_screen<MIXED>(xi - jx[w][jj], yi - jy[w][jj], zi - jz[w][jj], vxi - jvx[w][jj],
                                              vyi - jvy[w][jj], vzi - jvz[w][jj], mi + jm[w][jj], p, q, s64);
             const uint64_t bit = 1ull << jj;
             emask |= (d == ccs::SCREEN64_EDGE) ? bit : 0ull;
             umask |= (d == ccs::SCREEN64_UNSURE) ? bit : 0ull;
         }
-        // partners of this lane: j > i on the diagonal tile, all j otherwise
-        const int sh = lane + 1 - j0w;  // first partner bit with j > i
-        const uint64_t keep = !ivalid ? 0ull : (!diag || sh <= 0) ? ~0ull : (sh >= 64) ? 0ull : (~0ull << sh);
-        emask &= keep;
-        umask &= keep;
         ev = !ivalid ? 0 : (uint64_t)(diag ? max(0, jnw - max(0, sh)) : jnw);
         while (umask) {
             const int jj = __builtin_ctzll(umask);
@@ -802,6 +814,9 @@ __global__ __launch_bounds__(TPB) void k_kick_combine(SoA W, const Seg *__restri
 
 // Kick used by the cc_kick entry point: same sums, but velocities are written
 // to separate output arrays so that a failing call leaves the state untouched.
+// MIXED: FP32 pair forces on FP64 differences, Kahan-compensated over each
+// 256-partner tile, FP64 across tiles (the mixed-precision kick).
+template <bool MIXED>
 __global__ __launch_bounds__(TPB) void k_kick_all(SoA W, int n, const int32_t *__restrict__ label, double eps2,
                                                    double G, double *__restrict__ ax_out,
                                                    double *__restrict__ ay_out, double *__restrict__ az_out,
@@ -829,10 +844,23 @@ __global__ __launch_bounds__(TPB) void k_kick_all(SoA W, int n, const int32_t *_
         }
         __syncthreads();
         if (valid) {
-            for (int jj = 0; jj < jn; ++jj) {
-                const int j = jb + jj;
-                if (jl[jj] == li || j == i) continue;
-                ok &= accel_term(xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, G, ax, ay, az);
+            if (MIXED) {
+                Kahan3 k{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                const float e2 = (float)eps2;
+                for (int jj = 0; jj < jn; ++jj) {
+                    const int j = jb + jj;
+                    if (jl[jj] == li || j == i) continue;
+                    ok &= accel_term32(xi, yi, zi, jx[jj], jy[jj], jz[jj], (float)(G * jm[jj]), e2, k);
+                }
+                ax += (double)k.sx - (double)k.cx;
+                ay += (double)k.sy - (double)k.cy;
+                az += (double)k.sz - (double)k.cz;
+            } else {
+                for (int jj = 0; jj < jn; ++jj) {
+                    const int j = jb + jj;
+                    if (jl[jj] == li || j == i) continue;
+                    ok &= accel_term(xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, G, ax, ay, az);
+                }
             }
         }
     }
@@ -1097,6 +1125,7 @@ struct SmallKernel {
         unsigned long long tau = 0;
         const ScreenParams sq = screen_params(p, h);
         const ccs::Screen64 s64 = ccs::screen64_params(p.eta, h);
+        const ccs::Far64 f64 = ccs::far64_params(p.eta, h);
         // star test from each set's first position X
         for (int q = tid(); q < n; q += NT) {
             if (!is_main(L, q)) continue;
@@ -1118,9 +1147,13 @@ struct SmallKernel {
             const double xa = L.x[a], ya = L.y[a], za = L.z[a], vxa = L.vx[a], vya = L.vy[a], vza = L.vz[a],
                          ma = L.m[a];
             for (int b = a + 1; b < e; ++b) {
-                if (edge_decide<MIXED>(xa - L.x[b], ya - L.y[b], za - L.z[b], vxa - L.vx[b], vya - L.vy[b],
-                                       vza - L.vz[b], ma + L.m[b], p, sq, s64, h))
-                    lunite(L.par, a, b);
+                const double dx = xa - L.x[b], dy = ya - L.y[b], dz = za - L.z[b];
+                const double dvx = vxa - L.vx[b], dvy = vya - L.vy[b], dvz = vza - L.vz[b];
+                const double mb = L.m[b];
+                const double r2 = ((dx * dx + dy * dy) + dz * dz) + p.eps2;
+                const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
+                if (ccs::far64(r2, v2, p.G * (ma + mb), f64)) continue;  // certainly no edge
+                if (edge_decide<MIXED>(dx, dy, dz, dvx, dvy, dvz, ma + mb, p, sq, s64, h)) lunite(L.par, a, b);
             }
             tau += (unsigned long long)(e - a - 1);
         }
@@ -1746,10 +1779,15 @@ hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk
     return hipGetLastError();
 }
 
-hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, double *ax, double *ay,
-                           double *az, int32_t *err, hipStream_t st)
+hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, bool mixed, double *ax,
+                           double *ay, double *az, int32_t *err, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_kick_all, dim3(nblocks(n, 1 << 30)), dim3(TPB), 0, st, W, n, label, eps2, G, ax, ay, az, err);
+    if (mixed)
+        hipLaunchKernelGGL(k_kick_all<true>, dim3(nblocks(n, 1 << 30)), dim3(TPB), 0, st, W, n, label, eps2, G, ax, ay,
+                           az, err);
+    else
+        hipLaunchKernelGGL(k_kick_all<false>, dim3(nblocks(n, 1 << 30)), dim3(TPB), 0, st, W, n, label, eps2, G, ax,
+                           ay, az, err);
     return hipGetLastError();
 }
 

@@ -89,8 +89,9 @@ hipError_t launch_kick_tiles(SoA W, const GridLevelArgs &a, const KickBlock *blk
                              int njobs, const KickTile *ktile, const int32_t *labp, const uint8_t *singp, double h,
                              double eps2, double G, bool mixed, double *part, int32_t *parent, int32_t *cnt_next,
                              int32_t *err, uint64_t *stats, hipStream_t st);
-hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, double *ax, double *ay,
-                           double *az, int32_t *err, hipStream_t st);
+// cc_kick's sums into separate arrays (mixed: FP32 pair forces, Kahan per tile)
+hipError_t launch_kick_all(SoA W, int n, const int32_t *label, double eps2, double G, bool mixed, double *ax,
+                           double *ay, double *az, int32_t *err, hipStream_t st);
 hipError_t launch_apply_kick(SoA W, int n, const double *ax, const double *ay, const double *az, double h,
                              hipStream_t st);
 // One launch for a level's on-chip components: nbp blocks of two-particle

@@ -26,3 +26,19 @@ extern "C" void screen64_pairs(const double *x, const double *y, const double *z
         out[k] = ccs::screen64(r2, v2, rv, mu, s);
     }
 }
+
+// Far-pair test: 1 when it certifies "no edge", 0 when it leaves the pair to the screen.
+extern "C" void far64_pairs(const double *x, const double *y, const double *z, const double *vx, const double *vy,
+                            const double *vz, const double *m, const int32_t *pi, const int32_t *pj, int64_t npairs,
+                            const double *h, double eta, double eps2, double G, int32_t *out)
+{
+    for (int64_t k = 0; k < npairs; ++k) {
+        const int i = pi[k], j = pj[k];
+        const double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+        const double dvx = vx[i] - vx[j], dvy = vy[i] - vy[j], dvz = vz[i] - vz[j];
+        const double r2 = ((dx * dx + dy * dy) + dz * dz) + eps2;
+        const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
+        const double mu = G * (m[i] + m[j]);
+        out[k] = ccs::far64(r2, v2, mu, ccs::far64_params(eta, h[k])) ? 1 : 0;
+    }
+}

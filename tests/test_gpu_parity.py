@@ -420,11 +420,31 @@ def test_diagnostics_match_oracle():
 # ------------------------------------------------------------------ fast kick order
 
 def rel_close(got: dict, ref, rtol, what=""):
+    """Per particle: |a_i - b_i| <= rtol * |b_i| for every coordinate, with a
+    floor of 1e-6 of the field's largest value for coordinates that pass
+    through zero."""
     for f in ("x", "y", "z", "vx", "vy", "vz"):
         a, b = got[f], getattr(ref, f)
-        scale = np.max(np.abs(b)) + 1e-300
-        err = np.max(np.abs(a - b)) / scale
-        assert err <= rtol, f"{what} {f}: max rel err {err:.3e} > {rtol:.1e}"
+        floor = 1e-6 * (np.max(np.abs(b)) + 1e-300)
+        err = np.abs(a - b) / np.maximum(np.abs(b), floor)
+        k = int(np.argmax(err))
+        assert err[k] <= rtol, f"{what} {f}: particle {k} rel err {err[k]:.3e} > {rtol:.1e}"
+
+
+def kick_magnitude_sums(s, p, idx=None):
+    """sum_j |a_ij| per particle (the per-particle scale of the force
+    tolerance): the oracle's acceleration of each particle from each partner
+    alone, summed in magnitude."""
+    n = s.n
+    idx = np.arange(n) if idx is None else np.asarray(idx)
+    pos = s.pos()
+    out = np.empty(len(idx))
+    for k, i in enumerate(idx):
+        d = pos - pos[i]
+        r2 = np.einsum("ij,ij->i", d, d) + p.eps2
+        r2[i] = np.inf
+        out[k] = np.sum(p.G * s.m / r2)   # |a_ij| = G m_j r / (r^2 + eps^2)^(3/2) <= G m_j / (r^2 + eps^2)
+    return out
 
 
 @pytest.mark.parametrize("n", [257, 3000, 12000])
@@ -443,10 +463,12 @@ def test_fast_kick_all_slow_level_within_tolerance(n):
     g = State.from_numpy(s)
     st = ctx_for(p, kick_order=CC_ORDER_FAST, small_max=64).evolve(g, 1 / 64, 1 / 64)
     got = g.to_numpy()
+    # per particle: |dv_gpu - dv_ref| <= 1e-12 h sum_j |a_ij|
+    scale = 1e-12 * (1 / 64) * kick_magnitude_sums(s, p)
     for f in ("vx", "vy", "vz"):
         dv_ref = getattr(ref, f) - getattr(s, f)
         dv = got[f] - getattr(s, f)
-        assert np.max(np.abs(dv - dv_ref)) <= 1e-12 * np.max(np.abs(dv_ref))
+        assert np.all(np.abs(dv - dv_ref) <= scale), f
     assert st["kick_pairs"] == n * (n - 1) // 2
 
 
@@ -556,7 +578,9 @@ def test_mixed_step_conservation_and_accuracy(cfg, n):
     ctx = ctx_for(p, precision=CC_MIXED)
     ctx.evolve(g, 1 / 64, 1 / 64)
     got = g.to_numpy()
-    rel_close(got, ref, 1e-5, "mixed")
+    # FP32 pair forces (about 1e-7 relative each) move a particle whose
+    # velocity is small against the kicks it receives by more, relative to it
+    rel_close(got, ref, 1e-4, "mixed")
     d0 = oracle.diagnostics(s, p)
     gp = Particles(**got)
     d1 = oracle.diagnostics(gp, p)
@@ -567,35 +591,178 @@ def test_mixed_step_conservation_and_accuracy(cfg, n):
 
 # ------------------------------------------------------------------ full sizes
 
-def _sampled_component_check(s, lab, h, p, nsample, seed):
-    """Every edge (tau < h, from the oracle, one particle against all others)
-    at sampled particles joins particles of one component, and labels are
-    canonical (the smallest index of the component)."""
+def _oracle_neighbours(s, i, h, p):
+    n = s.n
+    tau = oracle.pair_timesteps(s, np.full(n, i, dtype=np.int32), np.arange(n, dtype=np.int32), p)
+    tau[i] = np.inf
+    return np.flatnonzero(tau < h)
+
+
+def _oracle_component(s, i, h, p, cap):
+    """The component of i in the oracle's graph {tau < h}, by breadth-first
+    search over the oracle's pair time steps (each visited particle against
+    all n); None once it holds more than cap particles."""
+    reached = {int(i)}
+    frontier = [int(i)]
+    while frontier:
+        nxt = []
+        for f in frontier:
+            for j in _oracle_neighbours(s, f, h, p):
+                if int(j) not in reached:
+                    reached.add(int(j))
+                    nxt.append(int(j))
+            if len(reached) > cap:
+                return None
+        frontier = nxt
+    return reached
+
+
+def _sampled_component_check(s, lab, h, p, nsample, seed, bfs_cap=64):
+    """At sampled particles: every oracle edge (tau < h) joins particles of one
+    GPU component (no component split too far), and for components of up to
+    bfs_cap particles the oracle's breadth-first search from the particle
+    reaches exactly the GPU component (no two components fused); labels are
+    canonical (the smallest index of the component).  Returns how many
+    components were compared whole."""
     n = s.n
     assert np.all(lab <= np.arange(n)) and np.all(lab[lab] == lab)
+    sizes = np.bincount(lab, minlength=n)
     rng = np.random.default_rng(seed)
+    whole = 0
     for i in rng.choice(n, nsample, replace=False):
-        pj = np.arange(n, dtype=np.int32)
-        pi = np.full(n, i, dtype=np.int32)
-        tau = oracle.pair_timesteps(s, pi, pj, p)
-        tau[i] = np.inf
-        nb = np.flatnonzero(tau < h)
+        nb = _oracle_neighbours(s, i, h, p)
         assert np.all(lab[nb] == lab[i]), f"particle {i}: neighbours in other components"
+        if sizes[lab[i]] <= bfs_cap:
+            comp = _oracle_component(s, i, h, p, bfs_cap)
+            assert comp is not None, f"particle {i}: oracle component larger than the GPU's"
+            want = set(np.flatnonzero(lab == lab[i]).tolist())
+            assert comp == want, f"particle {i}: GPU component {sorted(want)[:8]} != oracle {sorted(comp)[:8]}"
+            whole += 1
+    return whole
 
 
 @pytest.mark.parametrize("precision", [CC_FP64, CC_MIXED])
-@pytest.mark.parametrize("cfg", [3, 5])
-def test_split_full_size_sampled(cfg, precision):
-    """Top-level split of the 65 536-body fractal and the 262 144-body Plummer
-    workloads at dt = 1/64, in the sweep configuration the integrator uses."""
+@pytest.mark.parametrize("cfg,h", [(3, 1 / 64), (3, 2.0 ** -12), (5, 1 / 64), (5, 2.0 ** -15)])
+def test_split_full_size_sampled(cfg, h, precision):
+    """Splits of the 65 536-body fractal and the 262 144-body Plummer
+    workloads at the top pivot step and at a deep one, in the sweep
+    configuration the integrator uses: sampled particles' oracle edges stay
+    inside their GPU components, and small components match the oracle's
+    breadth-first search whole."""
     s = synth.workload(cfg)
     p = oracle.Params(eta=0.01)
     ctx = ctx_for(p, precision=precision, screen=CC_SCREEN_FP32 if precision == CC_MIXED else 0)
-    lab, nt = ctx.split_labels(State.from_numpy(s), 1 / 64)
+    lab, nt = ctx.split_labels(State.from_numpy(s), h)
     lab = lab.cpu().numpy()
-    _sampled_component_check(s, lab, 1 / 64, p, nsample=48, seed=cfg)
+    whole = _sampled_component_check(s, lab, h, p, nsample=48, seed=cfg)
     sizes = np.bincount(lab, minlength=s.n)
     assert nt == int(np.count_nonzero(sizes >= 2))
+    if h < 1 / 64:
+        assert whole >= 24   # at the deep step most sampled particles sit in small components
+
+
+def test_split_full_partition_fractal_deep_step():
+    """The whole partition of the 65 536-body fractal at h = 2^-12 against the
+    oracle's breadth-first search (about 2e9 oracle pair steps)."""
+    s = synth.workload(3)
+    p = oracle.Params(eta=0.01)
+    h = 2.0 ** -12
+    lab, nt = ctx_for(p).split_labels(State.from_numpy(s), h)
+    want, want_nt, _ = oracle.split_labels(s, h, p)
+    assert np.array_equal(lab.cpu().numpy(), want)
+    assert nt == want_nt
+
+
+@pytest.mark.parametrize("n,small_max,seed", [(450, 512, 31), (900, 1024, 32)])
+def test_on_chip_large_components_bitwise(n, small_max, seed):
+    """Sets of 257-1024 bodies run whole on chip (the 512- and 1024-slot LDS
+    layouts); one global step bit-identical to the oracle."""
+    s = synth.plummer(n, seed, masses="salpeter")
+    p = oracle.Params(eta=0.01)
+    got, ref, st, ost = run_both(s, 1 / 64, 1 / 64, p, small_max=small_max)
+    assert_state_equal(got, ref, f"n={n} small_max={small_max}")
+    for k in STAT_KEYS:
+        assert st[k] == ost[k], (k, st[k], ost[k])
+
+
+def _load_golden_step():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "plummer16k_salpeter_one_step.txt")
+    stats, rows = {}, []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# stats"):
+                for kv in line[len("# stats"):].split():
+                    k, v = kv.split("=")
+                    stats[k] = float(v) if "." in v else int(v)
+            elif not line.startswith("#"):
+                t = line.split()
+                rows.append([int(t[0])] + [float.fromhex(x) for x in t[1:]])
+    return stats, np.array(rows, dtype=object)
+
+
+def test_fast_order_full_size_plummer16k_step():
+    """One FAST-order global step of the full 16 384-body Salpeter Plummer
+    workload (the secondary benchmark) against the oracle's step (stored at
+    512 sampled particles by tests/golden/make_plummer16k_step.py): every
+    sampled coordinate within 1e-10 relative and the statistics identical."""
+    ost, rows = _load_golden_step()
+    s = synth.workload(2)
+    p = oracle.Params(eta=0.01)
+    g = State.from_numpy(s)
+    st = ctx_for(p, kick_order=CC_ORDER_FAST).evolve(g, 1 / 64, 1 / 64)
+    got = g.to_numpy()
+    idx = np.array([int(r[0]) for r in rows])
+    for c, f in enumerate(("x", "y", "z", "vx", "vy", "vz")):
+        want = np.array([float(r[1 + c]) for r in rows])
+        floor = 1e-6 * np.max(np.abs(want))
+        err = np.abs(got[f][idx] - want) / np.maximum(np.abs(want), floor)
+        assert err.max() <= 1e-10, (f, int(idx[np.argmax(err)]), err.max())
+    for k in STAT_KEYS:
+        assert st[k] == ost[k], (k, st[k], ost[k])
+
+
+@pytest.mark.parametrize("cfg,dt", [(3, 1 / 64), (5, 1 / 512)])
+def test_full_size_step_conserves_momenta(cfg, dt):
+    """One global step of the 65 536-body fractal (dt = 1/64) and the
+    262 144-body Plummer workload with hard binaries (dt = 1/512, the
+    benchmarked step): linear and angular momentum conserved to rounding
+    (every kick is applied to both members of a pair) and the energy error
+    small, from the library's diagnostics (pinned against the oracle's)."""
+    s = synth.workload(cfg)
+    p = oracle.Params(eta=0.01)
+    ctx = ctx_for(p, kick_order=CC_ORDER_FAST)
+    g = State.from_numpy(s)
+    d0 = ctx.diagnostics(g)
+    st = ctx.evolve(g, dt, dt)
+    d1 = ctx.diagnostics(g)
+    pscale = float(np.sum(s.m * np.linalg.norm(s.vel(), axis=1)))
+    lscale = float(np.sum(s.m * np.linalg.norm(np.cross(s.pos(), s.vel()), axis=1)))
+    assert np.linalg.norm(d1["P"] - d0["P"]) <= 1e-13 * pscale
+    assert np.linalg.norm(d1["L"] - d0["L"]) <= 1e-13 * lscale
+    # the integrator's own error over one step with 30% (10%) binaries at
+    # eta = 0.01: 1.8e-5 measured on the fractal, far below that with dt0 = 1/512
+    assert abs(d1["energy"] / d0["energy"] - 1) < 1e-4
+    assert st["components"] > 0 and st["max_depth_seen"] > 10
+
+
+def test_mixed_kick_force_error_full_size():
+    """The mixed-precision kick (FP32 pair forces, Kahan sums per tile) on the
+    262 144-body workload against the oracle's compensated FP64 sums at 128
+    sampled particles: rms relative error below 1e-6, none above 1e-4."""
+    s = synth.workload(5)
+    p = oracle.Params(eta=0.01)
+    z = s.copy()
+    for f in ("vx", "vy", "vz"):
+        getattr(z, f)[:] = 0.0
+    g = State.from_numpy(z)
+    ctx_for(p, precision=CC_MIXED).kick(g, 1.0)
+    got = g.to_numpy()
+    idx = np.random.default_rng(55).choice(s.n, 128, replace=False)
+    a = oracle.accel(s, idx, p, compensated=True)
+    am = np.stack([got["vx"][idx], got["vy"][idx], got["vz"][idx]], 1)
+    rel = np.linalg.norm(am - a, axis=1) / np.linalg.norm(a, axis=1)
+    assert np.sqrt(np.mean(rel ** 2)) < 1e-6 and rel.max() < 1e-4, (np.sqrt(np.mean(rel ** 2)), rel.max())
 
 
 def test_ensemble_full_size_sampled_clusters_bitwise():

@@ -20,12 +20,23 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 NO, EDGE, UNSURE = 0, 1, 2
 
 
+def _build_shim(tmp_path_factory, name, defines=()):
+    out = str(tmp_path_factory.mktemp(name) / f"lib{name}.so")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+                    *defines, os.path.join(HERE, "screen64_shim.cpp"), "-o", out], check=True)
+    return C.CDLL(out)
+
+
 @pytest.fixture(scope="module")
 def shim(tmp_path_factory):
-    out = str(tmp_path_factory.mktemp("screen64") / "libscreen64.so")
-    subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-                    os.path.join(HERE, "screen64_shim.cpp"), "-o", out], check=True)
-    return C.CDLL(out)
+    return _build_shim(tmp_path_factory, "screen64")
+
+
+@pytest.fixture(scope="module")
+def shim_cut(tmp_path_factory):
+    """The same header with the far-pair margin cut to one half (a planted
+    mistake: the bound then only guarantees tau >= h/2)."""
+    return _build_shim(tmp_path_factory, "screen64cut", ["-DCC_FAR64_MARGIN=0.5"])
 
 
 def _decide(shim, s, pi, pj, h, eta, eps2, G):
@@ -39,6 +50,19 @@ def _decide(shim, s, pi, pj, h, eta, eps2, G):
                         C.c_int64(len(pi)), d(h), C.c_double(eta), C.c_double(eps2), C.c_double(G),
                         out.ctypes.data_as(C.POINTER(C.c_int32)))
     return out
+
+
+def _far(shim, s, pi, pj, h, eta, eps2, G):
+    d = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
+    pi = np.ascontiguousarray(pi, np.int32)
+    pj = np.ascontiguousarray(pj, np.int32)
+    h = np.ascontiguousarray(h, np.float64)
+    out = np.zeros(len(pi), np.int32)
+    shim.far64_pairs(d(s.x), d(s.y), d(s.z), d(s.vx), d(s.vy), d(s.vz), d(s.m),
+                     pi.ctypes.data_as(C.POINTER(C.c_int32)), pj.ctypes.data_as(C.POINTER(C.c_int32)),
+                     C.c_int64(len(pi)), d(h), C.c_double(eta), C.c_double(eps2), C.c_double(G),
+                     out.ctypes.data_as(C.POINTER(C.c_int32)))
+    return out.astype(bool)
 
 
 def _pairs_state(rng, n):
@@ -126,3 +150,78 @@ def test_screen_zero_velocity_and_out_of_range(shim):
                    vz=np.zeros(2), m=np.ones(2))
     assert _decide(shim, s0, [0], [1], [0.1], 0.01, 0.0, 1.0)[0] == UNSURE
     assert _decide(shim, s, [0], [1], [2.0 ** -120], 0.01, 0.0, 1.0)[0] == UNSURE
+
+
+def _far_cases(rng, tau, n):
+    """Thresholds where a far-pair test is most exposed: just above tau (the
+    test must not certify "no edge" for a pair whose tau is below h), at tau
+    itself, and spread over decades on both sides."""
+    return {
+        "just_above": tau * (1.0 + rng.integers(1, 400, n) * 2.0 ** -52),
+        "up": np.nextafter(tau, np.inf),
+        "exact": tau.copy(),
+        "x1.001": tau * 1.001,
+        "x0.5": tau * 0.5,
+        "random": tau * 10.0 ** rng.uniform(-3, 3, n),
+    }
+
+
+@pytest.mark.parametrize("eta,eps2,G", [(0.01, 0.0, 1.0), (0.3, 0.0, 1.0), (1.0, 1e-8, 4.3e-3),
+                                         (0.003, 0.0, 1.0)])
+def test_far_test_never_contradicts_literal_test(shim, eta, eps2, G):
+    """Whenever the far-pair test certifies "no edge", the oracle's literal
+    tau is >= h; far from the threshold it certifies most pairs."""
+    rng = np.random.default_rng(9105 + int(eta * 1000))
+    n = 40000
+    s, pi, pj = _pairs_state(rng, n)
+    p = oracle.Params(eta=eta, eps2=eps2, G=G)
+    tau = oracle.pair_timesteps(s, pi, pj, p)
+    ok = (tau > 0) & np.isfinite(tau)
+    for name, h in _far_cases(rng, tau, n).items():
+        sel = ok & (h > 0) & np.isfinite(h)
+        far = _far(shim, s, pi[sel], pj[sel], h[sel], eta, eps2, G)
+        bad = far & (tau[sel] < h[sel])
+        assert not bad.any(), f"{name}: {bad.sum()} pairs certified far with tau < h"
+    # h well below every pair's tau: the test certifies the bulk of the pairs
+    h = tau / 64.0
+    sel = ok & (h >= 2.0 ** -60)
+    far = _far(shim, s, pi[sel], pj[sel], h[sel], eta, eps2, G)
+    assert far.mean() > 0.5, far.mean()
+
+
+def test_far_test_with_cut_margin_is_caught(shim_cut):
+    """Planted mistake: the far-pair header built with its margin cut to one
+    half certifies pairs whose tau lies just below h; the same cases find it.
+    (The conditions are sufficient ones, tight only at corners of the input
+    space, so cuts of a few per cent leave these random pairs decided alike.)"""
+    rng = np.random.default_rng(11)
+    n = 40000
+    s, pi, pj = _pairs_state(rng, n)
+    p = oracle.Params(eta=0.01)
+    tau = oracle.pair_timesteps(s, pi, pj, p)
+    ok = (tau > 0) & np.isfinite(tau)
+    wrong = 0
+    for name, h in _far_cases(rng, tau, n).items():
+        sel = ok & (h > 0) & np.isfinite(h)
+        far = _far(shim_cut, s, pi[sel], pj[sel], h[sel], 0.01, 0.0, 1.0)
+        wrong += int((far & (tau[sel] < h[sel])).sum())
+    assert wrong > 0
+
+
+def test_far_test_sweep_like_pairs(shim):
+    """Pairs of a Plummer sphere at the pivot steps of the deep levels: the
+    test agrees with the literal decision wherever it decides, and decides
+    most pairs at small h."""
+    from synth import plummer
+    s = plummer(3000, 5, masses="salpeter")
+    p = oracle.Params(eta=0.01)
+    rng = np.random.default_rng(3)
+    pi = rng.integers(0, s.n, 60000).astype(np.int32)
+    pj = ((pi + 1 + rng.integers(0, s.n - 1, 60000)) % s.n).astype(np.int32)
+    tau = oracle.pair_timesteps(s, pi, pj, p)
+    for k in range(0, 12, 2):
+        h = np.full(len(pi), 2.0 ** -(6 + k))
+        far = _far(shim, s, pi, pj, h, 0.01, 0.0, 1.0)
+        assert not (far & (tau < h)).any(), k
+        if k >= 6:
+            assert far.mean() > 0.9, (k, far.mean())
