@@ -145,6 +145,20 @@ int cc_split_labels(cc_ctx *ctx, const cc_state *s, int64_t n, double h,
  * flag before it applies the kick). */
 int cc_kick(cc_ctx *ctx, cc_state *s, int64_t n, const int32_t *label, double h, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cc_kick
+ * with its scratch (the three acceleration sums and the error flag) in a
+ * static device array of the library (1.5 MiB per device, held until the
+ * process ends), so the call allocates nothing on the device or the host.
+ * Same arguments, results and errors as cc_kick (bit-identical output), for
+ * 1 <= n <= CC_KICK_STATIC_MAX_N; a larger n fails with CC_ERR_ARG before
+ * any launch.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (several host threads, or several streams in flight)
+ * race and must not be issued.  Syncs on `stream` (it reads back the error
+ * flag before it applies the kick). */
+#define CC_KICK_STATIC_MAX_N 65536
+int cc_kick_static(cc_ctx *ctx, cc_state *s, int64_t n, const int32_t *label, double h, void *stream);
+
 /* Drift operator D_h (eq. 6): q_i += h v_i for every i with mask[i] != 0
  * (mask: device uint8[n], or NULL for every particle).  Asynchronous. */
 int cc_drift(cc_ctx *ctx, cc_state *s, int64_t n, const uint8_t *mask, double h, void *stream);

@@ -22,7 +22,7 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wno-unused-result", "-Wno-unused-value", "-Wno-unused-command-line-argument",
 ]
-SOURCES = ["cc_kernels.hip", "cc_api.cpp"]
+SOURCES = ["cc_kernels.hip", "cc_static.hip", "cc_api.cpp"]
 
 
 def build(verbose: bool = False) -> str:

@@ -19,10 +19,11 @@ CC_OK, CC_ERR_ARG, CC_ERR_NONFINITE, CC_ERR_DEPTH, CC_ERR_DEVICE, CC_ERR_OOM = 0
 CC_FP64, CC_MIXED = 0, 1
 CC_ORDER_FAST, CC_ORDER_EXACT = 0, 1
 CC_SCREEN_FP64, CC_SCREEN_FP32 = 0, 1
+KICK_STATIC_MAX_N = 65536   # CC_KICK_STATIC_MAX_N of include/cc.h
 
 # entry points declared in include/cc.h
 SYMBOLS = ("cc_create", "cc_destroy", "cc_set_params", "cc_last_error", "cc_pair_timesteps", "cc_split_labels",
-           "cc_kick", "cc_drift", "cc_evolve", "cc_evolve_batch", "cc_diagnostics", "cc_autotune",
+           "cc_kick", "cc_kick_static", "cc_drift", "cc_evolve", "cc_evolve_batch", "cc_diagnostics", "cc_autotune",
            "cc_timing_enable", "cc_timing_report")
 
 
@@ -77,6 +78,7 @@ def load_library():
     L.cc_pair_timesteps.argtypes = [vp, C.POINTER(_State), i64, vp, vp, i64, vp, vp]
     L.cc_split_labels.argtypes = [vp, C.POINTER(_State), i64, d, vp, C.POINTER(i64), vp]
     L.cc_kick.argtypes = [vp, C.POINTER(_State), i64, vp, d, vp]
+    L.cc_kick_static.argtypes = [vp, C.POINTER(_State), i64, vp, d, vp]
     L.cc_drift.argtypes = [vp, C.POINTER(_State), i64, vp, d, vp]
     L.cc_evolve.argtypes = [vp, C.POINTER(_State), i64, d, d, C.POINTER(_Stats), vp]
     L.cc_evolve_batch.argtypes = [vp, C.POINTER(_State), C.POINTER(i64), i32, d, d, C.POINTER(_Stats), vp]
@@ -205,6 +207,13 @@ class Context:
         if label is not None:
             label = label.to(device=s.m.device, dtype=torch.int32).contiguous()
         self._check(self._L.cc_kick(self._h, C.byref(s._c()), s.n, _ptr(label), h, _stream()))
+
+    def kick_static(self, s: State, h: float, label: torch.Tensor | None = None):
+        """cc_kick without any allocation (scratch in a static device array;
+        n <= KICK_STATIC_MAX_N)."""
+        if label is not None:
+            label = label.to(device=s.m.device, dtype=torch.int32).contiguous()
+        self._check(self._L.cc_kick_static(self._h, C.byref(s._c()), s.n, _ptr(label), h, _stream()))
 
     def drift(self, s: State, h: float, mask: torch.Tensor | None = None):
         if mask is not None:

@@ -1088,6 +1088,11 @@ int cc_create(cc_ctx **out, int32_t hip_device, const cc_params *p)
         delete c;
         return CC_ERR_DEVICE;
     }
+    // device address of cc_kick_static's scratch array (once per device)
+    if (ccg::static_scratch_setup(hip_device) != hipSuccess) {
+        delete c;
+        return CC_ERR_DEVICE;
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
         c->cus = cus;
@@ -1234,6 +1239,34 @@ int cc_kick(cc_ctx *c, cc_state *s, int64_t n, const int32_t *label, double h, v
     RC(sync_read_err(c));
     if (*c->h_err) return err_code(c, *c->h_err);
     HIPCHK(launch_apply_kick(S, (int)n, ax, ay, az, h, c->st));
+    return CC_OK;
+}
+
+int cc_kick_static(cc_ctx *c, cc_state *s, int64_t n, const int32_t *label, double h, void *stream)
+{
+    if (!c) return CC_ERR_ARG;
+    c->err.clear();
+    RC(check_state_ptrs(c, s));
+    if (n < 1) return fail(c, CC_ERR_ARG, "n must be >= 1");
+    if (n > CC_KICK_STATIC_MAX_N)
+        return fail(c, CC_ERR_ARG, "n = %lld exceeds the static scratch limit of %d particles", (long long)n,
+                    CC_KICK_STATIC_MAX_N);
+    if (!std::isfinite(h)) return fail(c, CC_ERR_ARG, "h must be finite");
+    HIPCHK(hipSetDevice(c->device));
+    // the address cc_create looked up for this device (never the array's name)
+    unsigned char *base = static_cast<unsigned char *>(ccg::static_scratch(c->device));
+    if (!base) return fail(c, CC_ERR_DEVICE, "static scratch of device %d was not set up", c->device);
+    double *ax = reinterpret_cast<double *>(base), *ay = ax + n, *az = ay + n;
+    int32_t *err = reinterpret_cast<int32_t *>(base + ccg::STATIC_ACC_BYTES);
+    hipStream_t st = (hipStream_t)stream;
+    SoA S = user_soa(s);
+    HIPCHK(launch_fill_i32(err, 1, 0, st));  // the previous call's flag is still there
+    HIPCHK(launch_kick_all(S, (int)n, label, c->params.eps2, c->params.G, mixed(c), ax, ay, az, err, st));
+    int32_t h_err = 0;
+    HIPCHK(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h_err) return err_code(c, h_err);
+    HIPCHK(launch_apply_kick(S, (int)n, ax, ay, az, h, st));
     return CC_OK;
 }
 

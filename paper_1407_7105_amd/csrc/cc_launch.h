@@ -105,6 +105,15 @@ hipError_t configure_items(int cap, int mode);
 hipError_t launch_items(SoA W, const SmallArgs &s, int cap, int mode, int nbp, int nbb, int nbw, double H,
                         DevParams p, int32_t *err, uint64_t *stats, uint64_t *fam, hipStream_t st);
 int diag_blocks(int n);
+
+// Static scratch of cc_kick_static (cc_static.hip): 3 x CC_KICK_STATIC_MAX_N
+// doubles of acceleration sums, then the error flag.
+constexpr size_t STATIC_ACC_BYTES = (size_t)3 * 65536 * sizeof(double);
+// With device `dev` current: look up (once per device) the scratch array's
+// device address.  cc_create calls it.
+hipError_t static_scratch_setup(int dev);
+// The scratch address on device `dev` (nullptr if never set up).
+void *static_scratch(int dev);
 hipError_t launch_diag(SoA S, int n, double eps2, double G, double *part, double *out, hipStream_t st);
 
 }  // namespace ccg
