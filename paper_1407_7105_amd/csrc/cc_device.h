@@ -367,7 +367,10 @@ __device__ __forceinline__ bool accel_term_rsq(double xi, double yi, double zi, 
 // The same term behind a mask, for loops without a branch per partner: a
 // partner that is off (same component, or the particle itself) contributes a
 // zero factor whatever its distance.  A coincident pair that is on gives a
-// non-finite sum, which the caller checks once.
+// non-finite sum, which the caller checks once.  One Newton step on the
+// hardware reciprocal square root: about 2^-46 relative per pair force,
+// against the fast order's bound of 1e-12 of the sum of the pair forces'
+// magnitudes per particle.
 __device__ __forceinline__ void accel_term_rsq_if(bool on, double xi, double yi, double zi, double xj, double yj,
                                                   double zj, double gmj, double eps2, double &ax, double &ay,
                                                   double &az)
@@ -379,9 +382,7 @@ __device__ __forceinline__ void accel_term_rsq_if(bool on, double xi, double yi,
     // an off partner sees r2 = 1 and mass 0: a finite zero factor
     const double rs = on ? r2 : 1.0;
     double y = __builtin_amdgcn_rsq(rs);
-    double e = __builtin_fma(-(rs * y), y, 1.0);
-    y = __builtin_fma(0.5 * y, e, y);
-    e = __builtin_fma(-(rs * y), y, 1.0);
+    const double e = __builtin_fma(-(rs * y), y, 1.0);
     y = __builtin_fma(0.5 * y, e, y);
     const double f = (on ? gmj : 0.0) * (y * (y * y));
     ax = __builtin_fma(f, dx, ax);

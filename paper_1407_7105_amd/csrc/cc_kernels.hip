@@ -9,6 +9,8 @@
 
 #include "cc_device.h"
 #include "cc_launch.h"
+#define CC_TILES_FN __device__ __forceinline__
+#include "cc_tiles.h"
 
 namespace ccg {
 
@@ -48,6 +50,13 @@ __device__ __forceinline__ void fam_add(uint64_t *fam, int idx, uint64_t v)
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// wave64 bitwise or of a uint64
+__device__ __forceinline__ uint64_t wave_or_u64(uint64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
     return v;
 }
 
@@ -111,6 +120,14 @@ __device__ __forceinline__ int32_t gunite(int32_t *par, int32_t a, int32_t b)
     }
     return a;
 }
+
+// Read-only views of the state in the constant address space: wave-uniform
+// loads through them become scalar loads into scalar registers.  Only for
+// kernels that do not write the arrays they read this way.
+typedef __attribute__((address_space(4))) const double CDouble;
+typedef __attribute__((address_space(4))) const int32_t CInt;
+__device__ __forceinline__ const CDouble *to_const(const double *p) { return (const CDouble *)(p); }
+__device__ __forceinline__ const CInt *to_const(const int32_t *p) { return (const CInt *)(p); }
 
 // LDS union-find (same rule: the smaller root becomes the parent)
 __device__ __forceinline__ bool bit_of(const uint32_t *w, int p) { return (w[p >> 5] >> (p & 31)) & 1u; }
@@ -266,6 +283,7 @@ __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg
 // particle whose local root has a different global root into the global
 // structure: at most one global union per particle per tile.
 constexpr int ST = 64;  // sweep tile edge (one wavefront)
+
 // Launches of up to split_tiles tiles split each tile's partners over JS = 4
 // wavefronts so that the partner loops are short (the host's tuned value; a
 // split in two for mid-size launches measured slower than none).
@@ -289,6 +307,7 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
     __shared__ double jx[NW][JW], jy[NW][JW], jz[NW][JW], jvx[NW][JW], jvy[NW][JW], jvz[NW][JW], jm[NW][JW];
     __shared__ int32_t lpar[TPW][2 * ST];
     __shared__ int32_t groot[TPW][2 * ST];
+    __shared__ uint32_t eflag[TPW][2 * ST / 32];  // slots of the tile that carry an edge
     const int w = threadIdx.x / ST, lane = threadIdx.x % ST;
     const int ts = w / JS, jpart = w % JS;
     const int tile = blockIdx.x * TPW + ts;
@@ -303,12 +322,7 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
     if (active) {
         g = seg[s];
         T = (g.n + ST - 1) / ST;
-        int t = tile - tile_off[s];
-        while (t >= T - ti) {
-            t -= T - ti;
-            ti++;
-        }
-        tj = ti + t;
+        cct::tri_tile(T, tile - tile_off[s], ti, tj);
     }
     const bool diag = (ti == tj);
     const int jn = active ? min(ST, g.n - tj * ST) : 0;
@@ -319,15 +333,18 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
     const int i = g.start + (ivalid ? il : 0);
     int32_t *lp = lpar[ts];
     int32_t *gr = groot[ts];
+    uint32_t *ef = eflag[ts];
     if (jpart == 0) {
         lp[lane] = lane;
-        gr[lane] = ivalid ? gfind(parent, i) : -1;
+        gr[lane] = -1;
+        if (lane < 2 * ST / 32) ef[lane] = 0;
     }
     if (lane < JW) {
         const int v = ST + j0w + lane;
         lp[v] = v;
         gr[v] = -1;
         if (lane < jnw) {
+            // this wavefront's partners, for its per-lane screen loop
             const int j = g.start + tj * ST + j0w + lane;
             jx[w][lane] = S.x[j];
             jy[w][lane] = S.y[j];
@@ -336,11 +353,10 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
             jvy[w][lane] = S.vy[j];
             jvz[w][lane] = S.vz[j];
             jm[w][lane] = S.m[j];
-            if (!diag) gr[v] = gfind(parent, j);
         }
     }
     __syncthreads();
-    uint64_t ev = 0;
+    uint64_t ev = 0, emask = 0;
     if (active) {
         const double xi = S.x[i], yi = S.y[i], zi = S.z[i];
         const double vxi = S.vx[i], vyi = S.vy[i], vzi = S.vz[i], mi = S.m[i];
@@ -351,22 +367,44 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
         // literal formula), then resolve the undecided pairs and link the
         // edges.  Stage one, uniform across the wavefront: the far-pair test
         // on r^2, |u|^2 and mu, which settles most pairs of the deep levels.
+        // The partners are the same for every lane: read them through the
+        // scalar cache into scalar registers (the sweep never writes the
+        // state), so the loop costs no LDS bandwidth.
+        const int jbase = __builtin_amdgcn_readfirstlane(g.start + tj * ST + j0w);
+        const CDouble *cx = to_const(S.x) + jbase, *cy = to_const(S.y) + jbase, *cz = to_const(S.z) + jbase;
+        const CDouble *cvx = to_const(S.vx) + jbase, *cvy = to_const(S.vy) + jbase, *cvz = to_const(S.vz) + jbase;
+        const CDouble *cm = to_const(S.m) + jbase;
+        const int jnu = __builtin_amdgcn_readfirstlane(jnw);
         uint64_t smask = 0;
-#pragma unroll 4
-        for (int jj = 0; jj < jnw; ++jj) {
-            const double dx = xi - jx[w][jj], dy = yi - jy[w][jj], dz = zi - jz[w][jj];
-            const double dvx = vxi - jvx[w][jj], dvy = vyi - jvy[w][jj], dvz = vzi - jvz[w][jj];
+        const auto far_bit = [&](int jj, double xj, double yj, double zj, double vxj, double vyj, double vzj,
+                                 double mj) -> uint64_t {
+            const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+            const double dvx = vxi - vxj, dvy = vyi - vyj, dvz = vzi - vzj;
             const double r2 = ((dx * dx + dy * dy) + dz * dz) + p.eps2;
             const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
-            const double mu = p.G * (mi + jm[w][jj]);
-            smask |= ccs::far64(r2, v2, mu, f64) ? 0ull : (1ull << jj);
+            const double mu = p.G * (mi + mj);
+            return ccs::far64(r2, v2, mu, f64) ? 0ull : (1ull << jj);
+        };
+        // chunks of four partners: their 28 values are loaded together (wide
+        // scalar loads, one wait), then tested; the last partners one by one
+        int j0 = 0;
+        for (; j0 + 4 <= jnu; j0 += 4) {
+            double X[4], Y[4], Z[4], VX[4], VY[4], VZ[4], M[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                X[k] = cx[j0 + k]; Y[k] = cy[j0 + k]; Z[k] = cz[j0 + k];
+                VX[k] = cvx[j0 + k]; VY[k] = cvy[j0 + k]; VZ[k] = cvz[j0 + k]; M[k] = cm[j0 + k];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) smask |= far_bit(j0 + k, X[k], Y[k], Z[k], VX[k], VY[k], VZ[k], M[k]);
         }
+        for (; j0 < jnu; ++j0) smask |= far_bit(j0, cx[j0], cy[j0], cz[j0], cvx[j0], cvy[j0], cvz[j0], cm[j0]);
         // partners of this lane: j > i on the diagonal tile, all j otherwise
         const int sh = lane + 1 - j0w;  // first partner bit with j > i
         const uint64_t keep = !ivalid ? 0ull : (!diag || sh <= 0) ? ~0ull : (sh >= 64) ? 0ull : (~0ull << sh);
         smask &= keep;
         // Stage two, each lane over its own open pairs: the certified screen.
-        uint64_t emask = 0, umask = 0;
+        uint64_t umask = 0;
         while (smask) {
             const int jj = __builtin_ctzll(smask);
             smask &= smask - 1;
@@ -389,6 +427,23 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
             const uint64_t all = keep & (jnw >= 64 ? ~0ull : ((1ull << jnw) - 1ull));
             if (emask != all) notstar[s] = epoch;
         }
+        // flag the slots that carry an edge: this lane's particle, and every
+        // partner some lane links to
+        if (emask) atomicOr(&ef[lane >> 5], 1u << (lane & 31));
+        const uint64_t any = wave_or_u64(emask);
+        if (lane == 0 && any) {
+            const int base = (diag ? 0 : ST) + j0w;  // slot of partner bit 0 (a multiple of JW)
+            atomicOr(&ef[base >> 5], (uint32_t)(any << (base & 31)));
+            if (JW > 32) atomicOr(&ef[(base >> 5) + 1], (uint32_t)(any >> 32));
+        }
+    }
+    __syncthreads();
+    // global roots of the flagged slots only: a tile without an edge (most
+    // tiles of the deep levels) makes no union-find access at all
+    if (jpart == 0 && ivalid && bit_of(ef, lane)) gr[lane] = gfind(parent, i);
+    if (lane < jnw && !diag && bit_of(ef, ST + j0w + lane)) gr[ST + j0w + lane] = gfind(parent, g.start + tj * ST + j0w + lane);
+    __syncthreads();
+    if (emask) {
         const int32_t gi = gr[lane];
         int32_t lr = lane;  // an ancestor of this particle in the local structure
         const int joff = (diag ? 0 : ST) + j0w;
@@ -704,7 +759,38 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
     const int32_t iu = (labp[ifirst] == labp[ilast]) ? labp[ifirst] : -1;
     double ax = 0.0, ay = 0.0, az = 0.0;
     bool ok = true;
-    for (int jb = jlo; jb < jhi; jb += TPB) {
+    if (!MIXED) {
+        // FP64: every wavefront reads the partners through the scalar cache
+        // into scalar registers (the kernel writes none of x, y, z, m, labp),
+        // four at a time, so the partner loop costs no LDS bandwidth and no
+        // barrier.  No branch per partner: partners of the own component add
+        // a zero factor; a coincident pair shows as a non-finite sum.
+        for (int jb = jlo; jb < jhi; jb += TPB) {
+            const int jn = min(TPB, jhi - jb);
+            const int jfirst = g.start + jb, jlast = g.start + jb + jn - 1;
+            if (iu >= 0 && labp[jfirst] == iu && labp[jlast] == iu) continue;  // uniform across the block
+            const int base = __builtin_amdgcn_readfirstlane(jfirst);
+            const int jnu = __builtin_amdgcn_readfirstlane(jn);
+            const CDouble *cx = to_const(W.x) + base, *cy = to_const(W.y) + base, *cz = to_const(W.z) + base;
+            const CDouble *cm = to_const(W.m) + base;
+            const CInt *cl = to_const(labp) + base;
+            int jj = 0;
+            for (; jj + 4 <= jnu; jj += 4) {
+                double X[4], Y[4], Z[4], M[4];
+                int32_t Lb[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    X[k] = cx[jj + k]; Y[k] = cy[jj + k]; Z[k] = cz[jj + k]; M[k] = cm[jj + k]; Lb[k] = cl[jj + k];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    accel_term_rsq_if(Lb[k] != li, xi, yi, zi, X[k], Y[k], Z[k], G * M[k], eps2, ax, ay, az);
+            }
+            for (; jj < jnu; ++jj)
+                accel_term_rsq_if(cl[jj] != li, xi, yi, zi, cx[jj], cy[jj], cz[jj], G * cm[jj], eps2, ax, ay, az);
+        }
+    }
+    for (int jb = jlo; MIXED && jb < jhi; jb += TPB) {
         const int jn = min(TPB, jhi - jb);
         const int jfirst = g.start + jb, jlast = g.start + jb + jn - 1;
         if (iu >= 0 && labp[jfirst] == iu && labp[jlast] == iu) continue;  // uniform across the block
@@ -731,12 +817,6 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
                 ax += (double)k.sx - (double)k.cx;
                 ay += (double)k.sy - (double)k.cy;
                 az += (double)k.sz - (double)k.cz;
-            } else {
-                // no branch per partner: partners of the own component add
-                // a zero factor; a coincident pair shows as a non-finite sum
-#pragma unroll 2
-                for (int jj = 0; jj < jn; ++jj)
-                    accel_term_rsq_if(jl[jj] != li, xi, yi, zi, jx[jj], jy[jj], jz[jj], jm[jj], eps2, ax, ay, az);
             }
         }
     }
