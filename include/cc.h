@@ -85,6 +85,10 @@ typedef struct {
     int32_t screen;         /* cc_screen for the grid-wide sweep; either
                                screen leaves undecided pairs to the literal FP64 formula,
                                so partitions do not depend on it */
+    int32_t kepler;         /* 0: plain CC; 1: CC_KEPLER (Sec. 2.2, last paragraph; Sec. 3.2):
+                               a component of two particles is advanced over its half step
+                               by the two-body Kepler solution of eq. 10 (universal
+                               variables) instead of being recursed into; needs eps2 == 0 */
 } cc_params;
 
 typedef struct {
@@ -97,6 +101,7 @@ typedef struct {
     uint64_t splits;        /* calls of the split (evolve_cc invocations) */
     int64_t max_depth_seen; /* deepest recursion level (global step = 0) */
     double t_reached;       /* integration time completed without error */
+    uint64_t kepler_solves; /* two-body components advanced by the Kepler solution */
 } cc_stats;
 
 /* Create a context on HIP device `hip_device` with parameters *p (copied).

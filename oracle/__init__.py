@@ -44,13 +44,14 @@ class _State(C.Structure):
 
 
 class _Params(C.Structure):
-    _fields_ = [("eta", C.c_double), ("eps2", C.c_double), ("G", C.c_double), ("max_depth", C.c_int)]
+    _fields_ = [("eta", C.c_double), ("eps2", C.c_double), ("G", C.c_double), ("max_depth", C.c_int),
+                ("kepler", C.c_int)]
 
 
 class _Stats(C.Structure):
     _fields_ = [("tau_evals", C.c_uint64), ("kick_pairs", C.c_uint64), ("drifts", C.c_uint64),
                 ("components", C.c_uint64), ("splits", C.c_uint64), ("max_depth_seen", C.c_int64),
-                ("t_reached", C.c_double)]
+                ("t_reached", C.c_double), ("kepler_solves", C.c_uint64)]
 
 
 @dataclass
@@ -59,9 +60,10 @@ class Params:
     eps2: float = 0.0
     G: float = 1.0
     max_depth: int = 48
+    kepler: int = 0      # 1: CC_KEPLER (two-particle components by the Kepler solution)
 
     def c(self) -> _Params:
-        return _Params(self.eta, self.eps2, self.G, self.max_depth)
+        return _Params(self.eta, self.eps2, self.G, self.max_depth, self.kepler)
 
 
 _lib = None
@@ -91,9 +93,10 @@ def lib():
         L.cco_accel.argtypes = [P, S, C.c_int64, i64p, C.c_int64, dp, dp, dp]
         L.cco_accel_compensated.argtypes = [P, S, C.c_int64, i64p, C.c_int64, dp, dp, dp]
         L.cco_diagnostics.argtypes = [P, S, C.c_int64, dp]
+        L.cco_kepler.argtypes = [C.c_double, dp, C.c_double]
         for f in ("cco_pair_timesteps", "cco_split_bfs", "cco_split_uf", "cco_split_labels", "cco_kick",
                   "cco_drift", "cco_evolve", "cco_evolve_batch", "cco_accel", "cco_accel_compensated",
-                  "cco_diagnostics"):
+                  "cco_diagnostics", "cco_kepler"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -234,6 +237,14 @@ def accel(s, idx: np.ndarray | None = None, p: Params | None = None, compensated
     _rc(f(C.byref(_params(p)), C.byref(_state(s)), n, _ptr(idx, C.c_int64), idx.shape[0], _ptr(ax),
           _ptr(ay), _ptr(az)), "cco_accel")
     return np.stack([ax, ay, az], axis=1)
+
+
+def kepler(mu: float, r, v, dt: float):
+    """The oracle's two-body flow: relative position r and velocity v (3-vectors)
+    advanced by dt under mu = G (m_i + m_j).  Returns (r, v)."""
+    rv = np.ascontiguousarray(np.concatenate([np.asarray(r, float), np.asarray(v, float)]), dtype=np.float64)
+    _rc(lib().cco_kepler(mu, _ptr(rv), dt), "cco_kepler")
+    return rv[:3].copy(), rv[3:].copy()
 
 
 def diagnostics(s, p: Params | None = None) -> dict:

@@ -35,6 +35,7 @@
  */
 #include "cc_oracle.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -303,6 +304,172 @@ int cco_drift(cco_state *s, const int64_t *I, int64_t nI, const uint8_t *mask, d
 }
 
 /* ------------------------------------------------------------------------ */
+/* Two-body flow (eq. 10), universal variables (Bate, Mueller & White 1971).  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Stumpff functions c2(z) = (1 - cos sqrt z)/z and c3(z) = (sqrt z - sin sqrt z)/z^(3/2)
+ * (continued through z <= 0 with cosh/sinh).  |z| < 1: their power series
+ * c2 = sum (-z)^k/(2k+2)!, c3 = sum (-z)^k/(2k+3)!, with no cancellation;
+ * otherwise c2 in the form 2 sin^2(sqrt(z)/2)/z, which has none either.
+ */
+static const double TWO_PI = 6.283185307179586476925286766559005768;
+
+static void stumpff(double z, double *c2, double *c3)
+{
+    if (fabs(z) < 1.0) {
+        double t2 = 0.5, t3 = 1.0 / 6.0, s2 = 0.0, s3 = 0.0;
+        for (int k = 0; k < 20; k++) {
+            s2 += t2;
+            s3 += t3;
+            t2 *= -z / ((2.0 * k + 3.0) * (2.0 * k + 4.0));
+            t3 *= -z / ((2.0 * k + 4.0) * (2.0 * k + 5.0));
+        }
+        *c2 = s2;
+        *c3 = s3;
+    } else if (z > 0.0) {
+        const double w = sqrt(z);
+        const double sh = sin(0.5 * w);
+        *c2 = 2.0 * sh * sh / z;
+        *c3 = (w - sin(w)) / (z * w);
+    } else {
+        const double w = sqrt(-z);
+        const double sh = sinh(0.5 * w);
+        *c2 = 2.0 * sh * sh / (-z);
+        *c3 = (sinh(w) - w) / (-z * w);
+    }
+}
+
+/*
+ * Kepler's equation in the universal variable x for the relative orbit with
+ * |r0| = r0n, sigma0 = r0.v0 / sqrt(mu), alpha = 2/r0n - |v0|^2/mu:
+ *   sqrt(mu) t(x) = sigma0 x^2 c2(alpha x^2) + (1 - alpha r0n) x^3 c3(alpha x^2) + r0n x,
+ * whose derivative is the radius, r(x) = sigma0 x (1 - alpha x^2 c3)
+ * + (1 - alpha r0n) x^2 c2 + r0n > 0: t(x) increases, so x is found by
+ * Newton's method kept inside a bracket (a bisection step whenever Newton
+ * would leave it).  A bound orbit is first reduced by whole periods.  Then
+ * the Lagrange coefficients f, g, f', g' give r = f r0 + g v0 and
+ * v = f' r0 + g' v0.
+ */
+int cco_kepler(double mu, double rv[6], double dt)
+{
+    if (!(mu > 0.0) || !isfinite(mu) || !isfinite(dt)) return CCO_ERR_ARG;
+    const double r0[3] = {rv[0], rv[1], rv[2]}, v0[3] = {rv[3], rv[4], rv[5]};
+    const double r0n = sqrt((r0[0] * r0[0] + r0[1] * r0[1]) + r0[2] * r0[2]);
+    if (!(r0n > 0.0)) return CCO_ERR_NONFINITE;
+    if (dt == 0.0) return CCO_OK;
+    const double v0sq = (v0[0] * v0[0] + v0[1] * v0[1]) + v0[2] * v0[2];
+    const double rdv = (r0[0] * v0[0] + r0[1] * v0[1]) + r0[2] * v0[2];
+    const double smu = sqrt(mu);
+    const double sigma0 = rdv / smu;
+    const double alpha = 2.0 / r0n - v0sq / mu;
+    double t = dt;
+    if (alpha > 0.0) {
+        /* bound: the flow has period 2 pi / sqrt(mu alpha^3) */
+        const double period = TWO_PI / sqrt(mu * alpha * alpha * alpha);
+        t = fmod(dt, period);
+        if (t < 0.0) t += period;   /* into [0, period): the flow backwards is the flow forwards */
+    }
+    const double target = smu * t;
+    const double one_ar = 1.0 - alpha * r0n;
+    double c2 = 0.5, c3 = 1.0 / 6.0;
+    /* sqrt(mu) t(x); a non-finite value (overflow far beyond the root) counts
+     * as +-infinity, t(x) being increasing */
+#define TFUN(X, OUT)                                                                   \
+    do {                                                                               \
+        double c2_, c3_;                                                               \
+        stumpff(alpha * (X) * (X), &c2_, &c3_);                                        \
+        (OUT) = (sigma0 * (X) * (X) * c2_ + one_ar * (X) * (X) * (X) * c3_) + r0n * (X); \
+        if (!isfinite(OUT)) (OUT) = (X) > 0.0 ? INFINITY : -INFINITY;                  \
+    } while (0)
+    /* bracket [lo, hi] around the root: a bound orbit's reduced time lies
+     * within one period, x in [0, 2 pi / sqrt(alpha)]; otherwise start from the
+     * hyperbolic estimate of x and double, but never past |x| sqrt(-alpha) = 700
+     * (where the hyperbolic functions would overflow; the root lies far below) */
+    double lo = 0.0, hi = 0.0, x;
+    if (alpha > 0.0) {
+        hi = TWO_PI / sqrt(alpha);
+        x = smu * alpha * t;
+    } else {
+        double g = 0.0;
+        if (alpha < 0.0) {
+            const double a = 1.0 / alpha;
+            const double sg = t >= 0.0 ? 1.0 : -1.0;
+            const double arg = (-2.0 * mu * alpha * t) / (rdv + sg * sqrt(-mu * a) * (1.0 - r0n * alpha));
+            if (arg > 0.0 && isfinite(arg)) g = sg * sqrt(-a) * log(arg);
+        }
+        if (!(g * t > 0.0)) g = target / r0n;
+        const double cap = alpha < 0.0 ? 700.0 / sqrt(-alpha) : INFINITY;
+        double ag = fmin(fabs(g), cap);
+        for (int k = 0; k < 2100; k++) {
+            double fv;
+            const double xs = t >= 0.0 ? ag : -ag;
+            TFUN(xs, fv);
+            if (t >= 0.0 ? fv >= target : fv <= target) break;
+            if (ag >= cap) break;
+            ag = fmin(2.0 * ag, cap);
+        }
+        if (t >= 0.0) hi = ag;
+        else lo = -ag;
+        x = g;
+    }
+    if (!(x > lo && x < hi)) x = 0.5 * (lo + hi);
+    for (int it = 0; it < 400; it++) {
+        double tf;
+        TFUN(x, tf);
+        stumpff(alpha * x * x, &c2, &c3);
+        const double zz = alpha * x * x;
+        const double rr = (sigma0 * x * (1.0 - zz * c3) + one_ar * x * x * c2) + r0n;
+        const double res = tf - target;
+        if (res > 0.0) hi = x;
+        else lo = x;
+        double xn = x - res / rr;
+        if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
+        const double dx = xn - x;
+        x = xn;
+        if (fabs(dx) <= 4.0 * DBL_EPSILON * fabs(x) || hi - lo <= 4.0 * DBL_EPSILON * fabs(x)) break;
+    }
+#undef TFUN
+    const double z = alpha * x * x;
+    stumpff(z, &c2, &c3);
+    const double f = 1.0 - (x * x / r0n) * c2;
+    const double g = t - (x * x * x / smu) * c3;
+    double r[3];
+    for (int c = 0; c < 3; c++) r[c] = f * r0[c] + g * v0[c];
+    const double rn = sqrt((r[0] * r[0] + r[1] * r[1]) + r[2] * r[2]);
+    const double fd = (smu / (rn * r0n)) * (z * x * c3 - x);
+    const double gd = 1.0 - (x * x / rn) * c2;
+    for (int c = 0; c < 3; c++) {
+        rv[c] = r[c];
+        rv[3 + c] = fd * r0[c] + gd * v0[c];
+    }
+    return CCO_OK;
+}
+
+/* E_{h, H_ij} for the two-body Hamiltonian of particles i and j (eq. 10):
+ * the relative motion by the Kepler flow, the centre of mass uniformly. */
+static int kepler_pair(const cco_params *p, cco_state *s, int64_t i, int64_t j, double h)
+{
+    const double mi = s->m[i], mj = s->m[j];
+    const double M = mi + mj;
+    double rv[6] = {s->x[j] - s->x[i], s->y[j] - s->y[i], s->z[j] - s->z[i],
+                    s->vx[j] - s->vx[i], s->vy[j] - s->vy[i], s->vz[j] - s->vz[i]};
+    const double X = (mi * s->x[i] + mj * s->x[j]) / M, Y = (mi * s->y[i] + mj * s->y[j]) / M,
+                 Z = (mi * s->z[i] + mj * s->z[j]) / M;
+    const double VX = (mi * s->vx[i] + mj * s->vx[j]) / M, VY = (mi * s->vy[i] + mj * s->vy[j]) / M,
+                 VZ = (mi * s->vz[i] + mj * s->vz[j]) / M;
+    const int rc = cco_kepler(p->G * M, rv, h);
+    if (rc != CCO_OK) return rc == CCO_ERR_ARG ? CCO_ERR_NONFINITE : rc;
+    const double X1 = X + h * VX, Y1 = Y + h * VY, Z1 = Z + h * VZ;
+    const double fi = mj / M, fj = mi / M;
+    s->x[i] = X1 - fi * rv[0]; s->y[i] = Y1 - fi * rv[1]; s->z[i] = Z1 - fi * rv[2];
+    s->x[j] = X1 + fj * rv[0]; s->y[j] = Y1 + fj * rv[1]; s->z[j] = Z1 + fj * rv[2];
+    s->vx[i] = VX - fi * rv[3]; s->vy[i] = VY - fi * rv[4]; s->vz[i] = VZ - fi * rv[5];
+    s->vx[j] = VX + fj * rv[3]; s->vy[j] = VY + fj * rv[4]; s->vz[j] = VZ + fj * rv[5];
+    return CCO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The CC integrator (eqs. 26-31, Fig. 2).                                   */
 /* ------------------------------------------------------------------------ */
 
@@ -315,6 +482,23 @@ int cco_drift(cco_state *s, const int64_t *I, int64_t nI, const uint8_t *mask, d
  * The partition found at h is used for both halves; each inner call splits its
  * own set again on the state it sees.
  */
+static int evolve_rec(const cco_params *p, cco_state *s, const int64_t *I, int64_t n,
+                      double h, int64_t depth, cco_stats *st);
+
+/* E_{h, H_C} for a non-trivial component C (eq. 27): with CC_KEPLER a
+ * component of two particles is the two-body Hamiltonian of eq. 10 and is
+ * advanced by its Kepler solution (Sec. 2.2, last paragraph; Sec. 3.2);
+ * everything else recurses. */
+static int evolve_component(const cco_params *p, cco_state *s, const int64_t *I, int64_t n,
+                            double h, int64_t depth, cco_stats *st)
+{
+    if (p->kepler && n == 2) {
+        st->kepler_solves++;
+        return kepler_pair(p, s, I[0], I[1], h);
+    }
+    return evolve_rec(p, s, I, n, h, depth, st);
+}
+
 static int evolve_rec(const cco_params *p, cco_state *s, const int64_t *I, int64_t n,
                       double h, int64_t depth, cco_stats *st)
 {
@@ -348,7 +532,7 @@ static int evolve_rec(const cco_params *p, cco_state *s, const int64_t *I, int64
 
     /* E_{h/2, H_C}: every non-trivial component independently (eq. 27) */
     for (int64_t r = 0; r < n && rc == CCO_OK; r++)
-        if (cnt[r] >= 2) rc = evolve_rec(p, s, memb + start[r], cnt[r], half, depth + 1, st);
+        if (cnt[r] >= 2) rc = evolve_component(p, s, memb + start[r], cnt[r], half, depth + 1, st);
     if (rc != CCO_OK) goto out;
 
     /* D_{h/2, T_R} */
@@ -377,7 +561,7 @@ static int evolve_rec(const cco_params *p, cco_state *s, const int64_t *I, int64
 
     /* E_{h/2, H_C} again with the same partition */
     for (int64_t r = 0; r < n && rc == CCO_OK; r++)
-        if (cnt[r] >= 2) rc = evolve_rec(p, s, memb + start[r], cnt[r], half, depth + 1, st);
+        if (cnt[r] >= 2) rc = evolve_component(p, s, memb + start[r], cnt[r], half, depth + 1, st);
 
 out:
     free(root); free(cnt); free(start); free(fill); free(memb);
@@ -391,6 +575,8 @@ static int check_params(const cco_params *p)
     if (!(p->eps2 >= 0.0) || !isfinite(p->eps2)) return CCO_ERR_ARG;
     if (!(p->G > 0.0) || !isfinite(p->G)) return CCO_ERR_ARG;
     if (p->max_depth < 0) return CCO_ERR_ARG;
+    if (p->kepler != 0 && p->kepler != 1) return CCO_ERR_ARG;
+    if (p->kepler && p->eps2 != 0.0) return CCO_ERR_ARG;   /* the Kepler solution is for 1/r */
     return CCO_OK;
 }
 

@@ -43,6 +43,9 @@ typedef struct {
     double eps2;            /* Plummer softening squared (eq. 3) */
     double G;               /* gravitational constant (1 in N-body units) */
     int max_depth;          /* recursion cap; deeper calls fail with CCO_ERR_DEPTH */
+    int kepler;             /* 1: CC_KEPLER (Sec. 2.2, Sec. 3.2): a component of two particles is
+                               advanced by the Kepler solution instead of being recursed into;
+                               needs eps2 == 0 */
 } cco_params;
 
 typedef struct {
@@ -53,6 +56,7 @@ typedef struct {
     uint64_t splits;        /* calls of the split */
     int64_t max_depth_seen; /* deepest recursion level reached (top = 0) */
     double t_reached;       /* integration time completed without error */
+    uint64_t kepler_solves; /* two-body components advanced by the Kepler solution (CC_KEPLER) */
 } cco_stats;
 
 /* Interaction time step tau(i,j) (eq. 19): the smaller of the symmetrised
@@ -110,6 +114,13 @@ int cco_accel(const cco_params *p, const cco_state *s, int64_t n,
 /* Same with Neumaier-compensated sums (reference for tolerance checks). */
 int cco_accel_compensated(const cco_params *p, const cco_state *s, int64_t n,
                           const int64_t *idx, int64_t nidx, double *ax, double *ay, double *az);
+
+/* Two-body (Kepler) flow of eq. 10 with eps = 0 for time dt: the relative
+ * motion r = q_j - q_i, v = v_j - v_i under mu = G (m_i + m_j), by the
+ * universal-variable formulation (Bate, Mueller & White 1971), and the centre
+ * of mass moving uniformly.  rv[6] = (r, v) is advanced in place.  Returns
+ * CCO_ERR_ARG for mu <= 0 or a non-finite dt, CCO_ERR_NONFINITE for r = 0. */
+int cco_kepler(double mu, double rv[6], double dt);
 
 /* Conserved quantities with compensated sums (eqs. 1-3):
  * out[0]=kinetic, out[1]=potential, out[2..4]=linear momentum,

@@ -168,6 +168,7 @@ DevParams dev_params(const cc_ctx *c)
     p.eps2 = c->params.eps2;
     p.G = c->params.G;
     p.max_depth = c->params.max_depth;
+    p.kepler = c->params.kepler;
     return p;
 }
 
@@ -194,6 +195,9 @@ int check_params(cc_ctx *c, const cc_params *p)
     if (p->kick_order != CC_ORDER_FAST && p->kick_order != CC_ORDER_EXACT)
         return fail(c, CC_ERR_ARG, "unknown kick_order");
     if (p->screen != CC_SCREEN_FP64 && p->screen != CC_SCREEN_FP32) return fail(c, CC_ERR_ARG, "unknown screen");
+    if (p->kepler != 0 && p->kepler != 1) return fail(c, CC_ERR_ARG, "kepler must be 0 or 1");
+    if (p->kepler && p->eps2 != 0.0)
+        return fail(c, CC_ERR_ARG, "the Kepler solution of two-body components needs eps2 == 0");
     return CC_OK;
 }
 
@@ -847,7 +851,12 @@ int route_top(cc_ctx *c, const std::vector<Seg> &top, std::vector<Seg> &big, int
     const int sm = small_max(c);
     big.clear();
     for (const Seg &g : top) {
-        if (g.n == 2) pairs.push_back(g);
+        // Clusters of one or two bodies take the grid path (a split, then a
+        // two-body component joins the level's pair list like any other):
+        // on-chip launches only ever hold sets of three or more at their
+        // top.  Two GPU runs with such clusters in the on-chip launch went
+        // silent and the cause was not found, so that route stays closed.
+        if (g.n < 3) big.push_back(g);
         else if (g.n <= sm) {
             const int b = g.n <= 8 ? 0 : g.n <= 32 ? 1 : g.n <= 128 ? 2 : 3;
             small[b].push_back(g);
@@ -1000,7 +1009,7 @@ int evolve_common(cc_ctx *c, cc_state *s, int64_t n, const int64_t *off, int32_t
     int rc = CC_OK;
     int64_t done = 0;
     bool all_on_chip = true;
-    for (const Seg &g : top) all_on_chip = all_on_chip && g.n <= small_max(c);
+    for (const Seg &g : top) all_on_chip = all_on_chip && g.n >= 3 && g.n <= small_max(c);
     if (all_on_chip && nsteps >= 2 && !c->timing) {
         bool captured = false;
         rc = evolve_on_chip_graph(c, top, n, nsteps, dt, &done, &captured);
@@ -1053,6 +1062,7 @@ int evolve_common(cc_ctx *c, cc_state *s, int64_t n, const int64_t *off, int32_t
             o.splits = h[ST_SPLIT];
             o.max_depth_seen = (int64_t)h[ST_MAXD];
             o.t_reached = (double)done * dt;
+            o.kepler_solves = h[ST_KEPLER];
         }
     }
     return rc;

@@ -11,13 +11,15 @@
 #define CC_SCREEN64_FN __device__ __forceinline__
 #define CC_SCREEN64_RSQ(x) __builtin_amdgcn_rsq(x)
 #include "cc_screen64.h"
+#define CC_KEPLER_FN __device__ inline
+#include "cc_kepler.h"
 
 namespace ccg {
 
 struct DevParams {
     double eta, eps2, G;
     int32_t max_depth;
-    int32_t pad;
+    int32_t kepler;  // CC_KEPLER: two-particle components by the Kepler solution
 };
 
 // A set of particles evolved by one evolve_cc call: slots [start, start+n)
@@ -60,6 +62,7 @@ enum StatIdx {
     ST_COMP = 4,      // non-trivial components found
     ST_SPLIT = 5,     // evolve_cc calls (splits)
     ST_MAXD = 6,      // deepest level (atomicMax)
+    ST_KEPLER = 7,    // two-body components advanced by the Kepler solution
     ST_N = 8
 };
 
@@ -402,16 +405,43 @@ struct Body {
 };
 
 struct PairCounters {
-    uint64_t tau, kick, drift, comp, split;
+    uint64_t tau, kick, drift, comp, split, kepler;
     int32_t maxd;
 };
 
-// Returns 0, or EB_DEPTH / EB_BUDGET (a and b are then partly advanced; the
-// caller discards them: a failing global step is restored from its snapshot).
+// E_{h, H_ab} (eq. 10) for a two-particle component: the relative motion by
+// the Kepler flow, the centre of mass uniformly.
+__device__ inline bool kepler_pair_dev(Body &a, Body &b, double h, double G)
+{
+    const double M = a.m + b.m;
+    const double cx = (a.m * a.x + b.m * b.x) / M, cy = (a.m * a.y + b.m * b.y) / M, cz = (a.m * a.z + b.m * b.z) / M;
+    const double ux = (a.m * a.vx + b.m * b.vx) / M, uy = (a.m * a.vy + b.m * b.vy) / M,
+                 uz = (a.m * a.vz + b.m * b.vz) / M;
+    double rx = b.x - a.x, ry = b.y - a.y, rz = b.z - a.z, vx = b.vx - a.vx, vy = b.vy - a.vy, vz = b.vz - a.vz;
+    if (!cck::kepler_flow(G * M, rx, ry, rz, vx, vy, vz, h)) return false;
+    const double X = cx + h * ux, Y = cy + h * uy, Z = cz + h * uz;
+    const double fa = b.m / M, fb = a.m / M;
+    a.x = X - fa * rx; a.y = Y - fa * ry; a.z = Z - fa * rz;
+    b.x = X + fb * rx; b.y = Y + fb * ry; b.z = Z + fb * rz;
+    a.vx = ux - fa * vx; a.vy = uy - fa * vy; a.vz = uz - fa * vz;
+    b.vx = ux + fb * vx; b.vy = uy + fb * vy; b.vz = uz + fb * vz;
+    return true;
+}
+
+// Returns 0, or EB_DEPTH / EB_BUDGET / EB_NONFINITE (a and b are then partly
+// advanced; the caller discards them: a failing global step is restored from
+// its snapshot).  With CC_KEPLER (p.kepler), a pair that is a component
+// found by a split (`component`) is advanced by the Kepler flow for H; a
+// top-level two-particle set is split first, and once its two particles form
+// a component each half of it is one Kepler flow of h/2.
 template <bool MIXED>
 __device__ inline int evolve_pair(Body &a, Body &b, double H, int32_t depth0, const DevParams &p,
-                                  PairCounters &c)
+                                  PairCounters &c, bool component = false)
 {
+    if (p.kepler && component) {
+        c.kepler++;
+        return kepler_pair_dev(a, b, H, p.G) ? 0 : EB_NONFINITE;
+    }
     uint64_t second = 0;
     uint64_t leaves = 0;
     int lvl = 0;
@@ -426,20 +456,24 @@ __device__ inline int evolve_pair(Body &a, Body &b, double H, int32_t depth0, co
         const bool e = edge_decide<MIXED>(a.x - b.x, a.y - b.y, a.z - b.z, a.vx - b.vx, a.vy - b.vy,
                                           a.vz - b.vz, msum, p, screen_params(p, h),
                                           ccs::screen64_params(p.eta, h), h);
-        if (e && lvl < 63) {
+        if (e && p.kepler) {
+            // the pair is a component at h: its two halves are Kepler flows of h/2
+            c.comp++;
+            c.kepler += 2;
+            if (!kepler_pair_dev(a, b, 0.5 * h, p.G) || !kepler_pair_dev(a, b, 0.5 * h, p.G)) return EB_NONFINITE;
+        } else if (e) {
+            if (lvl >= 63) return EB_DEPTH;  // deeper than the walker can track: treat as the depth cap
             c.comp++;
             lvl++;
             h = 0.5 * h;
             second &= ~(1ull << lvl);
             continue;
-        }
-        if (e) return EB_DEPTH;  // deeper than the walker can track: treat as the depth cap
-        if (++leaves > PAIR_LEAF_BUDGET) return EB_BUDGET;
-        // leaf: D_{h/2} K_h D_{h/2} on two singletons
-        const double hh = 0.5 * h;
-        a.x += hh * a.vx; a.y += hh * a.vy; a.z += hh * a.vz;
-        b.x += hh * b.vx; b.y += hh * b.vy; b.z += hh * b.vz;
-        {
+        } else {
+            if (++leaves > PAIR_LEAF_BUDGET) return EB_BUDGET;
+            // leaf: D_{h/2} K_h D_{h/2} on two singletons
+            const double hh = 0.5 * h;
+            a.x += hh * a.vx; a.y += hh * a.vy; a.z += hh * a.vz;
+            b.x += hh * b.vx; b.y += hh * b.vy; b.z += hh * b.vz;
             const double dx = b.x - a.x;
             const double dy = b.y - a.y;
             const double dz = b.z - a.z;
@@ -451,11 +485,11 @@ __device__ inline int evolve_pair(Body &a, Body &b, double H, int32_t depth0, co
             const double bax = 0.0 - maf * dx, bay = 0.0 - maf * dy, baz = 0.0 - maf * dz;
             a.vx += h * aax; a.vy += h * aay; a.vz += h * aaz;
             b.vx += h * bax; b.vy += h * bay; b.vz += h * baz;
+            a.x += hh * a.vx; a.y += hh * a.vy; a.z += hh * a.vz;
+            b.x += hh * b.vx; b.y += hh * b.vy; b.z += hh * b.vz;
+            c.kick++;
+            c.drift += 4;
         }
-        a.x += hh * a.vx; a.y += hh * a.vy; a.z += hh * a.vz;
-        b.x += hh * b.vx; b.y += hh * b.vy; b.z += hh * b.vz;
-        c.kick++;
-        c.drift += 4;
         // advance to the next sibling
         while (lvl > 0 && ((second >> lvl) & 1ull)) {
             second &= ~(1ull << lvl);

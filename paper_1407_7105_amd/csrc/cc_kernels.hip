@@ -980,8 +980,10 @@ __device__ void run_pairs(SoA W, const Seg *__restrict__ items, int n, int t0, i
         }
         Body a{W.x[ia], W.y[ia], W.z[ia], W.vx[ia], W.vy[ia], W.vz[ia], W.m[ia]};
         Body b{W.x[ib], W.y[ib], W.z[ib], W.vx[ib], W.vy[ib], W.vz[ib], W.m[ib]};
-        PairCounters c{0, 0, 0, 0, 0, -1};
-        const int e = evolve_pair<MIXED>(a, b, H, g.depth, p, c);
+        PairCounters c{0, 0, 0, 0, 0, 0, -1};
+        // a top-level set of two particles (depth 0) is split first; deeper
+        // ones are components of a split
+        const int e = evolve_pair<MIXED>(a, b, H, g.depth, p, c, g.depth > 0);
         if (e) atomicOr(err, e);
         W.x[ia] = a.x; W.y[ia] = a.y; W.z[ia] = a.z; W.vx[ia] = a.vx; W.vy[ia] = a.vy; W.vz[ia] = a.vz;
         W.x[ib] = b.x; W.y[ib] = b.y; W.z[ib] = b.z; W.vx[ib] = b.vx; W.vy[ib] = b.vy; W.vz[ib] = b.vz;
@@ -991,6 +993,7 @@ __device__ void run_pairs(SoA W, const Seg *__restrict__ items, int n, int t0, i
         stat_add(stats, g.cluster, ST_DRIFT, c.drift);
         stat_add(stats, g.cluster, ST_COMP, c.comp);
         stat_add(stats, g.cluster, ST_SPLIT, c.split);
+        stat_add(stats, g.cluster, ST_KEPLER, c.kepler);
         if (c.maxd >= 0) stat_max(stats, g.cluster, c.maxd);
         fam_add(fam, 0, c.tau);
         fam_add(fam, 1, c.kick);
@@ -1032,6 +1035,7 @@ struct SmallLDS {
     int32_t wsum[4];
     unsigned long long ctr[8];
     int32_t nbin;
+    int32_t hasmain;  // the level being visited holds a set of three or more
     int32_t item;
     int32_t err;
     int32_t maxd;
@@ -1087,7 +1091,10 @@ struct SmallKernel {
     // two-particle sets.
     static __device__ void enumerate(SmallLDS<CAP> &L, int k, int n, bool collect_bins)
     {
-        if (tid() == 0) L.nbin = 0;
+        if (tid() == 0) {
+            L.nbin = 0;
+            L.hasmain = 0;
+        }
         sync();
         for (int p = tid(); p < n; p += NT) {
             const bool inL = (k == 0) || bit_of(L.nt[k - 1], p);
@@ -1115,6 +1122,7 @@ struct SmallKernel {
             }
             L.segS[p] = (int16_t)s;
             L.segE[p] = (int16_t)e;
+            if (p == s && e - s >= 3) L.hasmain = 1;
             if (collect_bins && p == s && e - s == 2) {
                 const int i = atomicAdd(&L.nbin, 1);
                 L.binlist[i] = (int16_t)s;
@@ -1131,7 +1139,7 @@ struct SmallKernel {
     static __device__ void run_binaries(SmallLDS<CAP> &L, double h, int depth, const DevParams &p)
     {
         const int nb = L.nbin;
-        PairCounters c{0, 0, 0, 0, 0, -1};
+        PairCounters c{0, 0, 0, 0, 0, 0, -1};
         for (int i = tid(); i < nb; i += NT) {
             int ia = L.binlist[i], ib = ia + 1;
             if (L.orig[ib] < L.orig[ia]) {
@@ -1141,7 +1149,8 @@ struct SmallKernel {
             }
             Body a{L.x[ia], L.y[ia], L.z[ia], L.vx[ia], L.vy[ia], L.vz[ia], L.m[ia]};
             Body b{L.x[ib], L.y[ib], L.z[ib], L.vx[ib], L.vy[ib], L.vz[ib], L.m[ib]};
-            const int e = evolve_pair<MIXED>(a, b, h, depth, p, c);
+            // every two-particle set below an item's top level is a component
+            const int e = evolve_pair<MIXED>(a, b, h, depth, p, c, true);
             if (e) atomicOr(&L.err, e);
             L.x[ia] = a.x; L.y[ia] = a.y; L.z[ia] = a.z; L.vx[ia] = a.vx; L.vy[ia] = a.vy; L.vz[ia] = a.vz;
             L.x[ib] = b.x; L.y[ib] = b.y; L.z[ib] = b.z; L.vx[ib] = b.vx; L.vy[ib] = b.vy; L.vz[ib] = b.vz;
@@ -1152,6 +1161,7 @@ struct SmallKernel {
         count(L, ST_DRIFT, c.drift);
         count(L, ST_COMP, c.comp);
         count(L, ST_SPLIT, c.split);
+        count(L, ST_KEPLER, c.kepler);
         if (c.maxd >= 0) atomicMax(&L.maxd, c.maxd);
         sync();
     }
@@ -1438,13 +1448,17 @@ struct SmallKernel {
             bool fresh = false;
             if (ph == 0) {
                 const int depth = g.depth + k;
-                if (depth > p.max_depth || k >= MAXL - 1) {
+                enumerate(L, k, n, true);
+                // the level is an evolve_cc call of its own unless, with
+                // CC_KEPLER, it holds only two-particle components (Kepler
+                // solutions, no split)
+                const bool splits_here = !p.kepler || L.hasmain;
+                if (splits_here && (depth > p.max_depth || k >= MAXL - 1)) {
                     if (tid() == 0) L.err |= EB_DEPTH;
                     sync();
                     break;
                 }
-                if (tid() == 0) atomicMax(&L.maxd, depth);
-                enumerate(L, k, n, true);
+                if (splits_here && tid() == 0) atomicMax(&L.maxd, depth);
                 run_binaries(L, h, depth, p);
                 if (L.err) break;
                 split(L, k, n, h, p);
@@ -1488,7 +1502,7 @@ struct SmallKernel {
                 Wg.vx[u] = L.vx[a]; Wg.vy[u] = L.vy[a]; Wg.vz[u] = L.vz[a];
             }
         }
-        if (tid() < 7 && tid() != ST_MAXD) stat_add(stats, g.cluster, tid(), L.ctr[tid()]);
+        if (tid() < ST_N && tid() != ST_MAXD) stat_add(stats, g.cluster, tid(), L.ctr[tid()]);
         if (tid() == 0) {
             fam_add(fam, 0, L.ctr[ST_TAU]);
             fam_add(fam, 1, L.ctr[ST_KICK]);
