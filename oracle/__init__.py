@@ -45,7 +45,7 @@ class _State(C.Structure):
 
 class _Params(C.Structure):
     _fields_ = [("eta", C.c_double), ("eps2", C.c_double), ("G", C.c_double), ("max_depth", C.c_int),
-                ("kepler", C.c_int)]
+                ("kepler", C.c_int), ("hold", C.c_int)]
 
 
 class _Stats(C.Structure):
@@ -61,9 +61,10 @@ class Params:
     G: float = 1.0
     max_depth: int = 48
     kepler: int = 0      # 1: CC_KEPLER (two-particle components by the Kepler solution)
+    hold: int = 0        # 1: the HOLD split (fast particles recursed into as one set)
 
     def c(self) -> _Params:
-        return _Params(self.eta, self.eps2, self.G, self.max_depth, self.kepler)
+        return _Params(self.eta, self.eps2, self.G, self.max_depth, self.kepler, self.hold)
 
 
 _lib = None

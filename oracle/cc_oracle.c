@@ -568,6 +568,75 @@ out:
     return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* The HOLD split (Sec. 2.1, eqs. 11-17).                                    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * evolve_hold(H, h) for the particle set I (ascending):
+ *   tau(i) = min over j in I of tau(i,j)            particle time step
+ *   S = {i : tau(i) >= h}, F = {i : tau(i) < h}     (eqs. 11-12)
+ *   E_{h/2, H_F}                                    recursion at h/2 (eq. 14)
+ *   D_{h/2, T_S} K_{h, V_S + V_SF} D_{h/2, T_S}     (eqs. 15-17)
+ *   E_{h/2, H_F}
+ * tau(i) < h holds exactly when some tau(i,j) < h, which needs every pair
+ * (the HOLD split evaluates all interactions, Sec. 2.3).  F is recursed into
+ * as one closed set.  The recursion ends when F is empty.
+ */
+static int evolve_hold(const cco_params *p, cco_state *s, const int64_t *I, int64_t n,
+                       double h, int64_t depth, cco_stats *st)
+{
+    if (depth > p->max_depth) return CCO_ERR_DEPTH;
+    if (depth > st->max_depth_seen) st->max_depth_seen = depth;
+    st->splits++;
+    double *taui = (double *)malloc(sizeof(double) * (size_t)n);
+    int64_t *lab = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    int64_t *F = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!taui || !lab || !F) { free(taui); free(lab); free(F); return CCO_ERR_OOM; }
+    for (int64_t k = 0; k < n; k++) taui[k] = INFINITY;
+    for (int64_t a = 0; a < n; a++) {
+        for (int64_t b = a + 1; b < n; b++) {
+            const double t = cco_tau(p, s, I[a], I[b]);
+            st->tau_evals++;
+            if (t < taui[a]) taui[a] = t;
+            if (t < taui[b]) taui[b] = t;
+        }
+    }
+    /* labels for the kick: every fast particle carries -1, a slow one its
+     * position, so a pair is kicked unless both members are fast */
+    int64_t nf = 0;
+    for (int64_t k = 0; k < n; k++) {
+        if (taui[k] < h) { lab[k] = -1; F[nf++] = I[k]; }
+        else lab[k] = k;
+    }
+    const double half = 0.5 * h;
+    int rc = CCO_OK;
+    if (nf > 0) {
+        st->components++;
+        rc = evolve_hold(p, s, F, nf, half, depth + 1, st);
+    }
+    if (rc == CCO_OK) {
+        for (int64_t k = 0; k < n; k++) {
+            if (lab[k] < 0) continue;
+            const int64_t i = I[k];
+            s->x[i] += half * s->vx[i]; s->y[i] += half * s->vy[i]; s->z[i] += half * s->vz[i];
+            st->drifts++;
+        }
+        rc = cco_kick(p, s, I, n, lab, h, &st->kick_pairs);
+    }
+    if (rc == CCO_OK) {
+        for (int64_t k = 0; k < n; k++) {
+            if (lab[k] < 0) continue;
+            const int64_t i = I[k];
+            s->x[i] += half * s->vx[i]; s->y[i] += half * s->vy[i]; s->z[i] += half * s->vz[i];
+            st->drifts++;
+        }
+        if (nf > 0) rc = evolve_hold(p, s, F, nf, half, depth + 1, st);
+    }
+    free(taui); free(lab); free(F);
+    return rc;
+}
+
 static int check_params(const cco_params *p)
 {
     if (!p) return CCO_ERR_ARG;
@@ -577,6 +646,8 @@ static int check_params(const cco_params *p)
     if (p->max_depth < 0) return CCO_ERR_ARG;
     if (p->kepler != 0 && p->kepler != 1) return CCO_ERR_ARG;
     if (p->kepler && p->eps2 != 0.0) return CCO_ERR_ARG;   /* the Kepler solution is for 1/r */
+    if (p->hold != 0 && p->hold != 1) return CCO_ERR_ARG;
+    if (p->hold && p->kepler) return CCO_ERR_ARG;          /* the Kepler option belongs to the CC split */
     return CCO_OK;
 }
 
@@ -618,7 +689,7 @@ static int evolve_range(const cco_params *p, cco_state *s, int64_t lo, int64_t h
         rc = check_state(s, lo, hi);
         if (rc != CCO_OK) break;
         for (int c = 0; c < 6; c++) memcpy(snap + (size_t)c * n, arr[c] + lo, sizeof(double) * (size_t)n);
-        rc = evolve_rec(p, s, I, n, dt, 0, st);
+        rc = p->hold ? evolve_hold(p, s, I, n, dt, 0, st) : evolve_rec(p, s, I, n, dt, 0, st);
         if (rc == CCO_OK) rc = check_state(s, lo, hi);
         if (rc != CCO_OK) {
             for (int c = 0; c < 6; c++) memcpy(arr[c] + lo, snap + (size_t)c * n, sizeof(double) * (size_t)n);

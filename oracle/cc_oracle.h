@@ -46,6 +46,10 @@ typedef struct {
     int kepler;             /* 1: CC_KEPLER (Sec. 2.2, Sec. 3.2): a component of two particles is
                                advanced by the Kepler solution instead of being recursed into;
                                needs eps2 == 0 */
+    int hold;               /* 1: the HOLD split of Sec. 2.1 (eqs. 11-17) instead of the CC split:
+                               the fast set F = {i : tau(i) < h}, tau(i) = min_j tau(i,j), is
+                               recursed into as one set; pairs with a slow member are kicked
+                               (not with kepler) */
 } cco_params;
 
 typedef struct {
