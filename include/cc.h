@@ -89,12 +89,18 @@ typedef struct {
                                a component of two particles is advanced over its half step
                                by the two-body Kepler solution of eq. 10 (universal
                                variables) instead of being recursed into; needs eps2 == 0 */
+    int32_t hold;           /* 0: the CC split; 1: the HOLD split of Sec. 2.1 (eqs. 11-17): a
+                               particle is fast when its time step tau(i) = min_j tau(i,j) is
+                               below h, i.e. when it belongs to a non-trivial component; the
+                               fast particles of a set are recursed into as ONE set F and every
+                               pair with a slow member is kicked.  Not with kepler. */
 } cc_params;
 
 typedef struct {
     uint64_t tau_pairs;     /* pair time steps evaluated (all launches) */
     uint64_t tau_pairs_alg; /* pair time steps the split needs: n-1 per fully
-                               connected set, n(n-1)/2 otherwise (Sec. 2.3) */
+                               connected set, n(n-1)/2 otherwise (Sec. 2.3); the HOLD
+                               split always needs n(n-1)/2 */
     uint64_t kick_pairs;    /* unordered pairs kicked (label_i != label_j) */
     uint64_t drifts;        /* single-particle half-step drifts */
     uint64_t components;    /* non-trivial components produced by all splits */
@@ -172,7 +178,9 @@ int cc_drift(cc_ctx *ctx, cc_state *s, int64_t n, const uint8_t *mask, double h,
  *   evolve_cc(H, h): split at h; evolve_cc(C_k, h/2) for every non-trivial
  *   component; drift R by h/2; kick every pair in different components by h;
  *   drift R by h/2; evolve_cc(C_k, h/2) again with the same partition,
- * starting with h = dt on all n particles.  dt > 0, t_end/dt a positive
+ * starting with h = dt on all n particles (with params.hold the components of
+ * a set are merged into one set F before the recursion, Sec. 2.1).
+ * dt > 0, t_end/dt a positive
  * integer (t_end is the duration).  Updates x..vz in place; syncs.
  * On error the state is restored to the start of the failing global step and
  * out->t_reached tells how far the integration got.  out may be NULL. */

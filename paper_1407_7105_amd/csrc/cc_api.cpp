@@ -58,6 +58,7 @@ struct Level {
     Seg *pairs = nullptr;
     Seg *small[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t *notstar = nullptr;  // cap_seg: epoch of the visit that found the set not to be a star
+    int32_t *hold = nullptr;     // 2 x cap_seg: the HOLD split's label of F and its size per segment
     bool star_hint = false;      // the last visit found a star set: test for stars before sweeping
     // Report block, read back with one copy per visit: count[8] ([0] pairs,
     // [1..4] small bins, [5] big, [6] star segments, [7] error bits) followed
@@ -169,6 +170,7 @@ DevParams dev_params(const cc_ctx *c)
     p.G = c->params.G;
     p.max_depth = c->params.max_depth;
     p.kepler = c->params.kepler;
+    p.hold = c->params.hold;
     return p;
 }
 
@@ -198,6 +200,8 @@ int check_params(cc_ctx *c, const cc_params *p)
     if (p->kepler != 0 && p->kepler != 1) return fail(c, CC_ERR_ARG, "kepler must be 0 or 1");
     if (p->kepler && p->eps2 != 0.0)
         return fail(c, CC_ERR_ARG, "the Kepler solution of two-body components needs eps2 == 0");
+    if (p->hold != 0 && p->hold != 1) return fail(c, CC_ERR_ARG, "hold must be 0 or 1");
+    if (p->hold && p->kepler) return fail(c, CC_ERR_ARG, "the Kepler option belongs to the CC split, not to HOLD");
     return CC_OK;
 }
 
@@ -289,6 +293,7 @@ int ensure_level(cc_ctx *c, int k, size_t nseg)
     if (lv.cap_seg < nseg) {
         const size_t cs = std::max(nseg, (size_t)64);
         RC(dalloc(c, &lv.notstar, cs));
+        RC(dalloc(c, &lv.hold, 2 * cs));
         // no stale flag may equal a later visit's epoch
         HIPCHK(hipMemset(lv.notstar, 0, cs * sizeof(int32_t)));
         const size_t bytes = cs * sizeof(Seg) + 3 * (cs + 1) * sizeof(int32_t);
@@ -711,8 +716,12 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h, const 
     }
     {
         Span s(c, F_LABEL);
-        HIPCHK(launch_label(a, lv.notstar, c->parent, lv.label, cnt_of(c, k), c->keys, c->vals, lv.count, c->stats,
-                            c->st));
+        const bool hold = c->params.hold != 0;
+        HIPCHK(launch_label(a, lv.notstar, c->parent, lv.label, cnt_of(c, k), c->keys, c->vals, lv.count,
+                            hold ? lv.hold : nullptr, c->stats, c->st));
+        // HOLD (Sec. 2.1): the non-trivial components of each set become one
+        // set F before the sort makes it contiguous
+        if (hold) HIPCHK(launch_hold(a, lv.label, cnt_of(c, k), c->keys, lv.hold, c->st));
     }
     int bits = 0;
     {
@@ -1146,7 +1155,7 @@ void cc_destroy(cc_ctx *c)
     for (auto &lv : c->levels) {
         F(lv.label); F(lv.sing); F(lv.labp); F(lv.singp); F(lv.src); F(lv.pairs);
         for (auto *p : lv.small) F(p);
-        F(lv.rep); F(lv.notstar); F(lv.desc); F(lv.kick);
+        F(lv.rep); F(lv.notstar); F(lv.hold); F(lv.desc); F(lv.kick);
         FH(lv.h_rep); FH(lv.h_desc); FH(lv.h_kick);
         if (lv.kick_ev) hipEventDestroy(lv.kick_ev);
     }
@@ -1219,7 +1228,8 @@ int cc_split_labels(cc_ctx *c, const cc_state *s, int64_t n, double h, int32_t *
     HIPCHK(launch_uf_init(c->parent, cnt_of(c, 0), (int)n, c->st));
     HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, false, c->stats, nullptr,
                         c->st));
-    HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, cnt_of(c, 0), nullptr, nullptr, nullptr, c->stats, c->st));
+    HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, cnt_of(c, 0), nullptr, nullptr, nullptr, nullptr,
+                        c->stats, c->st));
     if (n_nontrivial_out) {
         // roots carry their component size in cnt (zeroed for every slot by the reset)
         std::vector<int32_t> cnt((size_t)n);

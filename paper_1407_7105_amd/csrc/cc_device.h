@@ -20,6 +20,7 @@ struct DevParams {
     double eta, eps2, G;
     int32_t max_depth;
     int32_t kepler;  // CC_KEPLER: two-particle components by the Kepler solution
+    int32_t hold;    // the HOLD split: all fast particles of a set form one set
 };
 
 // A set of particles evolved by one evolve_cc call: slots [start, start+n)
@@ -76,13 +77,17 @@ enum ErrBits { EB_DEPTH = 1, EB_NONFINITE = 2, EB_MASS = 4, EB_CAPACITY = 8, EB_
 //     need about 2^22 leaves over h = 1/128 (some 1800 orbits of about 2000
 //     leaves at eta = 0.01); 2^24 leaves take about 10 s on one lane;
 //   - level visits of one on-chip item in one launch (a visit is one split or
-//     one kick of a level in LDS, a few to tens of microseconds);
+//     one kick of a level in LDS, a few microseconds for a wavefront team):
+//     the HOLD split keeps sets of three or more fast bodies deep in the
+//     hierarchy (a hard binary with any third fast body): a cluster of the
+//     fractal ensemble workload makes some 1.8 million splits in one step at
+//     dt = 1/64 under HOLD, each two or three visits;
 //   - steps of one union-find walk: links point to smaller slots only, so a
 //     walk ends within the set size (at most 1024 in LDS; the global sets of
 //     the workloads hold at most 2^18 slots and path halving keeps the walks
 //     far shorter); retries of one union, each lost to another thread's link.
 constexpr uint64_t PAIR_LEAF_BUDGET = 1ull << 24;
-constexpr uint64_t ITEM_VISIT_BUDGET = 1ull << 20;
+constexpr uint64_t ITEM_VISIT_BUDGET = 1ull << 23;
 constexpr int FIND_BUDGET = 1 << 20;
 constexpr int UNITE_RETRIES = 1 << 16;
 constexpr int LDS_FIND_BUDGET = 1 << 11;

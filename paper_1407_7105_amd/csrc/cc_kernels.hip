@@ -478,7 +478,7 @@ __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, cons
                                                 int32_t *__restrict__ parent, int32_t *__restrict__ label,
                                                 int32_t *__restrict__ cnt, uint32_t *__restrict__ keys,
                                                 uint32_t *__restrict__ vals, int32_t *__restrict__ count,
-                                                uint64_t *stats)
+                                                int32_t *__restrict__ hold, uint64_t *stats)
 {
     const int s = find_seg(chunk_off, nseg, blockIdx.x);
     const Seg g = seg[s];
@@ -486,6 +486,10 @@ __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, cons
     const bool ns = notstar[s] == epoch;
     const bool valid = local < g.n;
     if (count && blockIdx.x == 0 && threadIdx.x < 8) count[threadIdx.x] = 0;
+    if (hold && local == 0) {
+        hold[2 * s] = INT32_MAX;
+        hold[2 * s + 1] = 0;
+    }
     int32_t l = -1;
     if (valid) {
         const int u = g.start + local;
@@ -510,10 +514,56 @@ __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, cons
     }
     if (local == 0) {
         const uint64_t n = (uint64_t)g.n;
-        stat_add(stats, g.cluster, ST_TAU_ALG, ns ? n * (n - 1) / 2 : n - 1);
+        // the HOLD split needs every particle's own time step: all pairs
+        stat_add(stats, g.cluster, ST_TAU_ALG, (ns || hold) ? n * (n - 1) / 2 : n - 1);
         stat_add(stats, g.cluster, ST_SPLIT, 1);
         stat_max(stats, g.cluster, g.depth);
     }
+}
+
+// HOLD split (Sec. 2.1, eqs. 11-12): a particle is fast when its own time
+// step min_j tau(i,j) is below h, which is exactly when its component at h is
+// non-trivial.  Per segment, the smallest fast slot becomes the label of F and
+// the fast particles are counted; each component speaks through its root (the
+// slot equal to its label), so one atomic per component.
+__global__ __launch_bounds__(TPB) void k_hold_fast(const Seg *__restrict__ seg, const int32_t *__restrict__ chunk_off,
+                                                    int nseg, const int32_t *__restrict__ label,
+                                                    const int32_t *__restrict__ cnt, int32_t *__restrict__ hold)
+{
+    const int s = find_seg(chunk_off, nseg, blockIdx.x);
+    const Seg g = seg[s];
+    const int local = (blockIdx.x - chunk_off[s]) * TPB + threadIdx.x;
+    if (local >= g.n) return;
+    const int u = g.start + local;
+    if (label[u] != u) return;
+    const int32_t c = cnt[u];
+    if (c >= 2) {
+        atomicMin(&hold[2 * s], u);
+        atomicAdd(&hold[2 * s + 1], c);
+    }
+}
+
+// Every fast particle takes F's label (entry-order labels and the sort keys);
+// F's label slot takes F's size.  The size written there is at least the
+// component size it replaces, so concurrent "is fast" tests read the same
+// answer either way.
+__global__ __launch_bounds__(TPB) void k_hold_relabel(const Seg *__restrict__ seg,
+                                                       const int32_t *__restrict__ chunk_off,
+                                                       const int32_t *__restrict__ act_off, int nseg,
+                                                       int32_t *__restrict__ label, int32_t *cnt,
+                                                       uint32_t *__restrict__ keys, const int32_t *__restrict__ hold)
+{
+    const int s = find_seg(chunk_off, nseg, blockIdx.x);
+    const Seg g = seg[s];
+    const int local = (blockIdx.x - chunk_off[s]) * TPB + threadIdx.x;
+    if (local >= g.n) return;
+    const int u = g.start + local;
+    const int32_t l = label[u];
+    if (__hip_atomic_load(&cnt[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 2) return;
+    const int32_t f = hold[2 * s];
+    label[u] = f;
+    keys[act_off[s] + local] = (uint32_t)f;
+    if (u == f) __hip_atomic_store(&cnt[u], hold[2 * s + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Work lists of a level, filled while its components are made contiguous.
@@ -1202,6 +1252,33 @@ struct SmallKernel {
         return s >= 0 && (L.segE[p] - s) >= 3;
     }
 
+    // HOLD split (Sec. 2.1, eqs. 11-12): the particles of a main set that
+    // have an edge (the members of its non-trivial components) are fast and
+    // form one set F, labelled by its first position.  par[] (free between
+    // the union-find and the scan) holds each set's first fast position and
+    // aux[] (free until the kick) the fast flags.
+    static __device__ void hold_merge(SmallLDS<CAP> &L, int n)
+    {
+        for (int a = tid(); a < n; a += NT) {
+            if (!is_main(L, a)) continue;
+            L.aux[a] = L.cnt[L.cid[a]] >= 2 ? 1 : 0;
+            if (a == L.segS[a]) L.par[a] = CAP;
+        }
+        sync();
+        for (int a = tid(); a < n; a += NT)
+            if (is_main(L, a) && L.aux[a]) atomicMin(&L.par[L.segS[a]], a);
+        sync();
+        for (int a = tid(); a < n; a += NT) {
+            if (!is_main(L, a)) continue;
+            if (L.aux[a]) L.cid[a] = (int16_t)L.par[L.segS[a]];
+            L.cnt[a] = 0;
+        }
+        sync();
+        for (int a = tid(); a < n; a += NT)
+            if (is_main(L, a)) atomicAdd(&L.cnt[L.cid[a]], 1);
+        sync();
+    }
+
     // Split every main set of L_k at h (eq. 20) and reorder it by component.
     static __device__ void split(SmallLDS<CAP> &L, int k, int n, double h, const DevParams &p)
     {
@@ -1258,6 +1335,7 @@ struct SmallKernel {
             atomicAdd(&L.cnt[lab], 1);
         }
         sync();
+        if (p.hold) hold_merge(L, n);
         scan_cnt(L);
         // destination of every position: components in label order, members
         // in position order
@@ -1280,7 +1358,7 @@ struct SmallKernel {
             if (a == s) {
                 const unsigned long long m = (unsigned long long)(L.segE[a] - s);
                 splits++;
-                alg += bit_of(L.flag, s) ? m * (m - 1) / 2 : m - 1;
+                alg += (bit_of(L.flag, s) || p.hold) ? m * (m - 1) / 2 : m - 1;
             }
         }
         count(L, ST_COMP, comps);
@@ -1776,10 +1854,22 @@ hipError_t launch_sweep(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t
 }
 
 hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,
-                        uint32_t *keys, uint32_t *vals, int32_t *count, uint64_t *stats, hipStream_t st)
+                        uint32_t *keys, uint32_t *vals, int32_t *count, int32_t *hold, uint64_t *stats,
+                        hipStream_t st)
 {
     hipLaunchKernelGGL(k_label, dim3(a.nchunks), dim3(TPB), 0, st, a.seg, a.chunk_off, a.act_off, a.nseg, notstar,
-                       a.epoch, parent, label, cnt, keys, vals, count, stats);
+                       a.epoch, parent, label, cnt, keys, vals, count, hold, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_hold(const GridLevelArgs &a, int32_t *label, int32_t *cnt, uint32_t *keys, int32_t *hold,
+                       hipStream_t st)
+{
+    hipLaunchKernelGGL(k_hold_fast, dim3(a.nchunks), dim3(TPB), 0, st, a.seg, a.chunk_off, a.nseg, label, cnt, hold);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_hold_relabel, dim3(a.nchunks), dim3(TPB), 0, st, a.seg, a.chunk_off, a.act_off, a.nseg,
+                       label, cnt, keys, hold);
     return hipGetLastError();
 }
 

@@ -63,7 +63,13 @@ hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, DevParam
 // labels and component sizes; with keys/vals the sort keys of the active
 // particles, with count the work-list counters cleared
 hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,
-                        uint32_t *keys, uint32_t *vals, int32_t *count, uint64_t *stats, hipStream_t st);
+                        uint32_t *keys, uint32_t *vals, int32_t *count, int32_t *hold, uint64_t *stats,
+                        hipStream_t st);
+// HOLD split: merge the non-trivial components of every segment into one set
+// F (labels, sort keys and the size of F; hold: 2 ints per segment, prepared
+// by launch_label)
+hipError_t launch_hold(const GridLevelArgs &a, int32_t *label, int32_t *cnt, uint32_t *keys, int32_t *hold,
+                       hipStream_t st);
 size_t sort_temp_bytes(int n);
 hipError_t launch_sort(void *temp, size_t temp_bytes, const uint32_t *keys_in, uint32_t *keys_out,
                        const uint32_t *vals_in, uint32_t *vals_out, int n, int end_bit, hipStream_t st);
