@@ -140,8 +140,8 @@ int cc_pair_timesteps(cc_ctx *ctx, const cc_state *s, int64_t n,
  * for each particle the smallest particle index of its component; a particle
  * is a trivial component iff no other particle shares its label.  If
  * n_nontrivial_out is not NULL it receives the number of components with at
- * least two particles (host int64; the call then syncs on `stream`).
- * h must be > 0 and finite. */
+ * least two particles (host int64).  The call syncs on `stream` (it reads
+ * back the error flag).  h must be > 0 and finite. */
 int cc_split_labels(cc_ctx *ctx, const cc_state *s, int64_t n, double h,
                     int32_t *label_out, int64_t *n_nontrivial_out, void *stream);
 

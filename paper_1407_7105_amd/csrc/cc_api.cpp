@@ -427,7 +427,8 @@ int err_code(cc_ctx *c, int bits)
     if (bits & EB_DEPTH) return fail(c, CC_ERR_DEPTH, "recursion deeper than max_depth = %d", c->params.max_depth);
     if (bits & EB_CAPACITY) return fail(c, CC_ERR_DEVICE, "internal work-list capacity exceeded");
     if (bits & EB_BUDGET)
-        return fail(c, CC_ERR_DEPTH, "a component needed more than the per-launch work budget of halvings");
+        return fail(c, CC_ERR_DEPTH, "a per-launch work budget ran out (halvings of a component, or steps of the "
+                                     "union-find)");
     return CC_OK;
 }
 
@@ -711,14 +712,14 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h, const 
     }
     {
         Span s(c, F_SWEEP);
-        HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, star_pass, c->stats,
-                            fam_ptr(c, F_SWEEP), c->st));
+        HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, star_pass, c->errf,
+                            c->st));
     }
     {
         Span s(c, F_LABEL);
         const bool hold = c->params.hold != 0;
         HIPCHK(launch_label(a, lv.notstar, c->parent, lv.label, cnt_of(c, k), c->keys, c->vals, lv.count,
-                            hold ? lv.hold : nullptr, c->stats, c->st));
+                            hold ? lv.hold : nullptr, star_pass, c->stats, fam_ptr(c, F_SWEEP), c->errf, c->st));
         // HOLD (Sec. 2.1): the non-trivial components of each set become one
         // set F before the sort makes it contiguous
         if (hold) HIPCHK(launch_hold(a, lv.label, cnt_of(c, k), c->keys, lv.hold, c->st));
@@ -1226,10 +1227,12 @@ int cc_split_labels(cc_ctx *c, const cc_state *s, int64_t n, double h, int32_t *
     const DevParams p = dev_params(c);
     SoA S = user_soa(s);
     HIPCHK(launch_uf_init(c->parent, cnt_of(c, 0), (int)n, c->st));
-    HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, false, c->stats, nullptr,
-                        c->st));
-    HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, cnt_of(c, 0), nullptr, nullptr, nullptr, nullptr,
-                        c->stats, c->st));
+    HIPCHK(hipMemsetAsync(c->errf, 0, sizeof(int32_t), c->st));
+    HIPCHK(launch_sweep(S, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, false, c->errf, c->st));
+    HIPCHK(launch_label(a, lv.notstar, c->parent, label_out, cnt_of(c, 0), nullptr, nullptr, nullptr, nullptr, false,
+                        c->stats, nullptr, c->errf, c->st));
+    RC(sync_read_err(c));
+    if (*c->h_err) return err_code(c, *c->h_err);
     if (n_nontrivial_out) {
         // roots carry their component size in cnt (zeroed for every slot by the reset)
         std::vector<int32_t> cnt((size_t)n);

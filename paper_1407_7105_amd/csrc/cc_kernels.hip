@@ -90,10 +90,12 @@ __device__ __forceinline__ void gstore(int32_t *p, int32_t v)
 }
 
 // Parent pointers only ever point to smaller slots, so a walk ends within
-// the segment size; the budget only guards against corrupted input.
+// the segment size; the budgets only guard against a corrupted structure and
+// set `over` when they run out (the caller reports EB_BUDGET: never a silent
+// wrong partition).
 __device__ __forceinline__ int32_t *pslot(int32_t *par, int32_t a) { return par + (size_t)a * PARENT_STRIDE; }
 
-__device__ __forceinline__ int32_t gfind(int32_t *par, int32_t a)
+__device__ __forceinline__ int32_t gfind(int32_t *par, int32_t a, bool &over)
 {
     for (int it = 0; it < FIND_BUDGET; ++it) {
         const int32_t q = gload(pslot(par, a));
@@ -102,14 +104,15 @@ __device__ __forceinline__ int32_t gfind(int32_t *par, int32_t a)
         if (g != q) gstore(pslot(par, a), g);  // path halving: g is an ancestor of a
         a = q;
     }
+    over = true;
     return a;
 }
 
-__device__ __forceinline__ int32_t gunite(int32_t *par, int32_t a, int32_t b)
+__device__ __forceinline__ int32_t gunite(int32_t *par, int32_t a, int32_t b, bool &over)
 {
     for (int it = 0; it < UNITE_RETRIES; ++it) {
-        a = gfind(par, a);
-        b = gfind(par, b);
+        a = gfind(par, a, over);
+        b = gfind(par, b, over);
         if (a == b) return a;
         if (a > b) {
             const int32_t t = a;
@@ -118,6 +121,7 @@ __device__ __forceinline__ int32_t gunite(int32_t *par, int32_t a, int32_t b)
         }
         if (atomicCAS(pslot(par, b), b, a) == b) return a;
     }
+    over = true;
     return a;
 }
 
@@ -144,7 +148,7 @@ __device__ __forceinline__ void lstore(int32_t *p, int32_t v)
 
 // Find with path halving: every pointer written is an ancestor of the node,
 // which keeps the structure valid under concurrent hooking.
-__device__ __forceinline__ int32_t lfind(int32_t *par, int32_t a)
+__device__ __forceinline__ int32_t lfind(int32_t *par, int32_t a, bool &over)
 {
     for (int it = 0; it < LDS_FIND_BUDGET; ++it) {
         const int32_t q = lload(&par[a]);
@@ -153,15 +157,16 @@ __device__ __forceinline__ int32_t lfind(int32_t *par, int32_t a)
         if (g != q) lstore(&par[a], g);
         a = q;
     }
+    over = true;
     return a;
 }
 
 // Joins the sets of a and b; returns the root of the joined set (as seen now).
-__device__ __forceinline__ int32_t lunite(int32_t *par, int32_t a, int32_t b)
+__device__ __forceinline__ int32_t lunite(int32_t *par, int32_t a, int32_t b, bool &over)
 {
     for (int it = 0; it < LDS_FIND_BUDGET; ++it) {
-        a = lfind(par, a);
-        b = lfind(par, b);
+        a = lfind(par, a, over);
+        b = lfind(par, b, over);
         if (a == b) return a;
         if (a > b) {
             const int32_t t = a;
@@ -170,6 +175,7 @@ __device__ __forceinline__ int32_t lunite(int32_t *par, int32_t a, int32_t b)
         }
         if (atomicCAS(&par[b], b, a) == b) return a;
     }
+    over = true;
     return a;
 }
 
@@ -284,6 +290,18 @@ __global__ __launch_bounds__(TPB) void k_star(SoA S, const Seg *__restrict__ seg
 // structure: at most one global union per particle per tile.
 constexpr int ST = 64;  // sweep tile edge (one wavefront)
 
+#ifndef SWEEP_WAVES
+#define SWEEP_WAVES 7
+#endif
+#ifndef FAR_UNROLL
+#define FAR_UNROLL 4
+#endif
+
+// A partner of the sweep's far-pair loop, with G m for the test's mu.
+struct alignas(16) Partner {
+    double x, y, z, m, vx, vy, vz, gm;
+};
+
 // Launches of up to split_tiles tiles split each tile's partners over JS = 4
 // wavefronts so that the partner loops are short (the host's tuned value; a
 // split in two for mid-size launches measured slower than none).
@@ -294,17 +312,19 @@ constexpr int ST = 64;  // sweep tile edge (one wavefront)
 // has few tiles).  The tile's edges are first linked in an LDS union-find over
 // its 2 ST particles, then merged into the global structure.
 template <bool MIXED, int JS>
-__global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ seg,
+__global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__restrict__ seg,
                                                 const int32_t *__restrict__ tile_off, int nseg,
                                                 int32_t *__restrict__ notstar, int32_t epoch, int star_pass,
                                                 int32_t *__restrict__ parent, DevParams p, double h,
-                                                uint64_t *stats, uint64_t *fam)
+                                                int32_t *err)
 {
     constexpr int NW = TPB / ST;   // wavefronts per block
     constexpr int TPW = NW / JS;   // tiles per block
     constexpr int JW = ST / JS;    // partners per wavefront
     static_assert(NW % JS == 0, "JS must divide the wavefronts of a block");
-    __shared__ double jx[NW][JW], jy[NW][JW], jz[NW][JW], jvx[NW][JW], jvy[NW][JW], jvz[NW][JW], jm[NW][JW];
+    // each wavefront's partners: one 64-byte record per partner, read by all
+    // lanes at once (a broadcast) in the far-pair loop
+    __shared__ Partner pj[NW][JW];
     __shared__ int32_t lpar[TPW][2 * ST];
     __shared__ int32_t groot[TPW][2 * ST];
     __shared__ uint32_t eflag[TPW][2 * ST / 32];  // slots of the tile that carry an edge
@@ -343,62 +363,74 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
         const int v = ST + j0w + lane;
         lp[v] = v;
         gr[v] = -1;
-        if (lane < jnw) {
-            // this wavefront's partners, for its per-lane screen loop
-            const int j = g.start + tj * ST + j0w + lane;
-            jx[w][lane] = S.x[j];
-            jy[w][lane] = S.y[j];
-            jz[w][lane] = S.z[j];
-            jvx[w][lane] = S.vx[j];
-            jvy[w][lane] = S.vy[j];
-            jvz[w][lane] = S.vz[j];
-            jm[w][lane] = S.m[j];
-        }
     }
-    __syncthreads();
-    uint64_t ev = 0, emask = 0;
+    // this wavefront's partners, and whether they and its own particles all
+    // lie in the far-pair test's box
+    bool inbox = true;
+    if (active && lane < jnw) {
+        const int j = g.start + tj * ST + j0w + lane;
+        Partner q;
+        q.x = S.x[j];
+        q.y = S.y[j];
+        q.z = S.z[j];
+        q.m = S.m[j];
+        q.vx = S.vx[j];
+        q.vy = S.vy[j];
+        q.vz = S.vz[j];
+        q.gm = p.G * q.m;
+        pj[w][lane] = q;
+        inbox = ccs::far64_in_box(q.x, q.y, q.z, q.vx, q.vy, q.vz, q.gm);
+    }
+    double xi = 0.0, yi = 0.0, zi = 0.0, vxi = 0.0, vyi = 0.0, vzi = 0.0, mi = 0.0;
     if (active) {
-        const double xi = S.x[i], yi = S.y[i], zi = S.z[i];
-        const double vxi = S.vx[i], vyi = S.vy[i], vzi = S.vz[i], mi = S.m[i];
+        xi = S.x[i];
+        yi = S.y[i];
+        zi = S.z[i];
+        vxi = S.vx[i];
+        vyi = S.vy[i];
+        vzi = S.vz[i];
+        mi = S.m[i];
+        if (ivalid) inbox &= ccs::far64_in_box(xi, yi, zi, vxi, vyi, vzi, p.G * mi);
+    }
+    const bool allbox = __all(inbox);
+    __syncthreads();
+    uint64_t emask = 0;
+    if (active) {
         const ScreenParams q = screen_params(p, h);
         const ccs::Screen64 s64 = ccs::screen64_params(p.eta, h);
         const ccs::Far64 f64 = ccs::far64_params(p.eta, h);
         // Decide every pair first (one bit per partner: edge, or left to the
         // literal formula), then resolve the undecided pairs and link the
         // edges.  Stage one, uniform across the wavefront: the far-pair test
-        // on r^2, |u|^2 and mu, which settles most pairs of the deep levels.
-        // The partners are the same for every lane: read them through the
-        // scalar cache into scalar registers (the sweep never writes the
-        // state), so the loop costs no LDS bandwidth.
-        const int jbase = __builtin_amdgcn_readfirstlane(g.start + tj * ST + j0w);
-        const CDouble *cx = to_const(S.x) + jbase, *cy = to_const(S.y) + jbase, *cz = to_const(S.z) + jbase;
-        const CDouble *cvx = to_const(S.vx) + jbase, *cvy = to_const(S.vy) + jbase, *cvz = to_const(S.vz) + jbase;
-        const CDouble *cm = to_const(S.m) + jbase;
+        // on r^2, |u|^2 and mu, which settles most pairs of the deep levels;
+        // partners are broadcast from LDS, eight per step, and their bits
+        // gathered eight at a time.  Outside the test's box (never for
+        // particles of a star cluster) every pair stays open.
+        const Partner *P = pj[w];
         const int jnu = __builtin_amdgcn_readfirstlane(jnw);
-        uint64_t smask = 0;
-        const auto far_bit = [&](int jj, double xj, double yj, double zj, double vxj, double vyj, double vzj,
-                                 double mj) -> uint64_t {
-            const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
-            const double dvx = vxi - vxj, dvy = vyi - vyj, dvz = vzi - vzj;
-            const double r2 = ((dx * dx + dy * dy) + dz * dz) + p.eps2;
-            const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
-            const double mu = p.G * (mi + mj);
-            return ccs::far64(r2, v2, mu, f64) ? 0ull : (1ull << jj);
-        };
-        // chunks of four partners: their 28 values are loaded together (wide
-        // scalar loads, one wait), then tested; the last partners one by one
-        int j0 = 0;
-        for (; j0 + 4 <= jnu; j0 += 4) {
-            double X[4], Y[4], Z[4], VX[4], VY[4], VZ[4], M[4];
+        uint64_t smask = jnu >= 64 ? ~0ull : ((1ull << jnu) - 1ull);
+        if (allbox && f64.on && p.eps2 <= 0x1p98) {
+            const double gmi = p.G * mi, eps2 = p.eps2;
+            smask = 0;
+            int j0 = 0;
+            for (; j0 + FAR_UNROLL <= jnu; j0 += FAR_UNROLL) {
+                uint32_t c = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                X[k] = cx[j0 + k]; Y[k] = cy[j0 + k]; Z[k] = cz[j0 + k];
-                VX[k] = cvx[j0 + k]; VY[k] = cvy[j0 + k]; VZ[k] = cvz[j0 + k]; M[k] = cm[j0 + k];
+                for (int k = 0; k < FAR_UNROLL; ++k) {
+                    const Partner r = P[j0 + k];
+                    const bool far = ccs::far64_boxed(xi - r.x, yi - r.y, zi - r.z, vxi - r.vx, vyi - r.vy,
+                                                      vzi - r.vz, gmi + r.gm, eps2, f64);
+                    c |= far ? 0u : (1u << k);
+                }
+                smask |= (uint64_t)c << j0;
             }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) smask |= far_bit(j0 + k, X[k], Y[k], Z[k], VX[k], VY[k], VZ[k], M[k]);
+            for (; j0 < jnu; ++j0) {
+                const Partner r = P[j0];
+                const bool far = ccs::far64_boxed(xi - r.x, yi - r.y, zi - r.z, vxi - r.vx, vyi - r.vy, vzi - r.vz,
+                                                  gmi + r.gm, eps2, f64);
+                smask |= far ? 0ull : (1ull << j0);
+            }
         }
-        for (; j0 < jnu; ++j0) smask |= far_bit(j0, cx[j0], cy[j0], cz[j0], cvx[j0], cvy[j0], cvz[j0], cm[j0]);
         // partners of this lane: j > i on the diagonal tile, all j otherwise
         const int sh = lane + 1 - j0w;  // first partner bit with j > i
         const uint64_t keep = !ivalid ? 0ull : (!diag || sh <= 0) ? ~0ull : (sh >= 64) ? 0ull : (~0ull << sh);
@@ -408,18 +440,18 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
         while (smask) {
             const int jj = __builtin_ctzll(smask);
             smask &= smask - 1;
-            const int d = edge_screen<MIXED>(xi - jx[w][jj], yi - jy[w][jj], zi - jz[w][jj], vxi - jvx[w][jj],
-                                             vyi - jvy[w][jj], vzi - jvz[w][jj], mi + jm[w][jj], p, q, s64);
+            const Partner &r = P[jj];
+            const int d = edge_screen<MIXED>(xi - r.x, yi - r.y, zi - r.z, vxi - r.vx, vyi - r.vy, vzi - r.vz,
+                                             mi + r.m, p, q, s64);
             const uint64_t bit = 1ull << jj;
             emask |= (d == ccs::SCREEN64_EDGE) ? bit : 0ull;
             umask |= (d == ccs::SCREEN64_UNSURE) ? bit : 0ull;
         }
-        ev = !ivalid ? 0 : (uint64_t)(diag ? max(0, jnw - max(0, sh)) : jnw);
         while (umask) {
             const int jj = __builtin_ctzll(umask);
             umask &= umask - 1;
-            if (edge_pair(xi - jx[w][jj], yi - jy[w][jj], zi - jz[w][jj], vxi - jvx[w][jj], vyi - jvy[w][jj],
-                          vzi - jvz[w][jj], mi + jm[w][jj], p, h))
+            const Partner &r = P[jj];
+            if (edge_pair(xi - r.x, yi - r.y, zi - r.z, vxi - r.vx, vyi - r.vy, vzi - r.vz, mi + r.m, p, h))
                 emask |= 1ull << jj;
         }
         if (ti == 0 && lane == 0) {
@@ -440,8 +472,10 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
     __syncthreads();
     // global roots of the flagged slots only: a tile without an edge (most
     // tiles of the deep levels) makes no union-find access at all
-    if (jpart == 0 && ivalid && bit_of(ef, lane)) gr[lane] = gfind(parent, i);
-    if (lane < jnw && !diag && bit_of(ef, ST + j0w + lane)) gr[ST + j0w + lane] = gfind(parent, g.start + tj * ST + j0w + lane);
+    bool over = false;  // a union-find budget ran out
+    if (jpart == 0 && ivalid && bit_of(ef, lane)) gr[lane] = gfind(parent, i, over);
+    if (lane < jnw && !diag && bit_of(ef, ST + j0w + lane))
+        gr[ST + j0w + lane] = gfind(parent, g.start + tj * ST + j0w + lane, over);
     __syncthreads();
     if (emask) {
         const int32_t gi = gr[lane];
@@ -451,21 +485,17 @@ __global__ __launch_bounds__(TPB) void k_sweep(SoA S, const Seg *__restrict__ se
             const int jj = __builtin_ctzll(emask);
             emask &= emask - 1;
             const int vj = joff + jj;
-            if (gr[vj] != gi) lr = lunite(lp, lr, vj);
+            if (gr[vj] != gi) lr = lunite(lp, lr, vj, over);
         }
     }
     __syncthreads();
     // merge the tile's local sets into the global structure
     for (int v = jpart * ST + lane; v < 2 * ST; v += JS * ST) {
         if (gr[v] < 0) continue;
-        const int r = lfind(lp, v);
-        if (r != v && gr[r] != gr[v]) gunite(parent, gr[v], gr[r]);
+        const int r = lfind(lp, v, over);
+        if (r != v && gr[r] != gr[v]) gunite(parent, gr[v], gr[r], over);
     }
-    ev = wave_sum_u64(ev);
-    if (lane == 0 && active) {
-        stat_add(stats, g.cluster, ST_TAU, ev);
-        fam_add(fam, 0, ev);
-    }
+    if (over) atomicOr(err, EB_BUDGET);
 }
 
 // Labels (smallest slot of the component) and component sizes.  With keys,
@@ -478,7 +508,8 @@ __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, cons
                                                 int32_t *__restrict__ parent, int32_t *__restrict__ label,
                                                 int32_t *__restrict__ cnt, uint32_t *__restrict__ keys,
                                                 uint32_t *__restrict__ vals, int32_t *__restrict__ count,
-                                                int32_t *__restrict__ hold, uint64_t *stats)
+                                                int32_t *__restrict__ hold, int star_pass, uint64_t *stats,
+                                                uint64_t *sweep_fam, int32_t *err)
 {
     const int s = find_seg(chunk_off, nseg, blockIdx.x);
     const Seg g = seg[s];
@@ -493,7 +524,9 @@ __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, cons
     int32_t l = -1;
     if (valid) {
         const int u = g.start + local;
-        l = ns ? gfind(parent, u) : g.start;
+        bool over = false;
+        l = ns ? gfind(parent, u, over) : g.start;
+        if (over) atomicOr(err, EB_BUDGET);
         label[u] = l;
         if (keys) {
             const int k = act_off[s] + local;
@@ -516,6 +549,12 @@ __global__ __launch_bounds__(TPB) void k_label(const Seg *__restrict__ seg, cons
         const uint64_t n = (uint64_t)g.n;
         // the HOLD split needs every particle's own time step: all pairs
         stat_add(stats, g.cluster, ST_TAU_ALG, (ns || hold) ? n * (n - 1) / 2 : n - 1);
+        // the sweep evaluated every pair of the segment unless a star pass
+        // ahead of it found the segment a star (counted here, once per
+        // segment, rather than by an atomic per sweep tile)
+        const uint64_t swept = (!star_pass || ns) ? n * (n - 1) / 2 : 0;
+        stat_add(stats, g.cluster, ST_TAU, swept);
+        fam_add(sweep_fam, 0, swept);
         stat_add(stats, g.cluster, ST_SPLIT, 1);
         stat_max(stats, g.cluster, g.depth);
     }
@@ -1016,11 +1055,32 @@ __global__ void k_apply_kick(SoA W, int n, const double *__restrict__ ax, const 
 // Two-particle components, one per lane.
 // ---------------------------------------------------------------------------
 // Two-particle components, one per thread: threads t0, t0 + nt, ... of the
-// caller take items t0, t0 + nt, ...
+// caller take items t0, t0 + nt, ...  Each thread sums its counters while its
+// items stay in one cluster; at the end a wavefront whose threads all hold
+// the same cluster adds its sums with one atomic per counter (the statistics
+// are a handful of words that every wavefront of the launch would otherwise
+// hit once per thread).
+__device__ __forceinline__ void pair_counters_flush(uint64_t *stats, uint64_t *fam, int cluster,
+                                                    const PairCounters &c)
+{
+    stat_add(stats, cluster, ST_TAU, c.tau);
+    stat_add(stats, cluster, ST_TAU_ALG, c.tau);
+    stat_add(stats, cluster, ST_KICK, c.kick);
+    stat_add(stats, cluster, ST_DRIFT, c.drift);
+    stat_add(stats, cluster, ST_COMP, c.comp);
+    stat_add(stats, cluster, ST_SPLIT, c.split);
+    stat_add(stats, cluster, ST_KEPLER, c.kepler);
+    if (c.maxd >= 0) stat_max(stats, cluster, c.maxd);
+    fam_add(fam, 0, c.tau);
+    fam_add(fam, 1, c.kick);
+}
+
 template <bool MIXED>
 __device__ void run_pairs(SoA W, const Seg *__restrict__ items, int n, int t0, int nt, double H, const DevParams &p,
                           int32_t *err, uint64_t *stats, uint64_t *fam)
 {
+    PairCounters tot{0, 0, 0, 0, 0, 0, -1};
+    int cl = -1;  // cluster of the sums in tot
     for (int it = t0; it < n; it += nt) {
         const Seg g = items[it];
         int ia = g.start, ib = g.start + 1;
@@ -1037,16 +1097,37 @@ __device__ void run_pairs(SoA W, const Seg *__restrict__ items, int n, int t0, i
         if (e) atomicOr(err, e);
         W.x[ia] = a.x; W.y[ia] = a.y; W.z[ia] = a.z; W.vx[ia] = a.vx; W.vy[ia] = a.vy; W.vz[ia] = a.vz;
         W.x[ib] = b.x; W.y[ib] = b.y; W.z[ib] = b.z; W.vx[ib] = b.vx; W.vy[ib] = b.vy; W.vz[ib] = b.vz;
-        stat_add(stats, g.cluster, ST_TAU, c.tau);
-        stat_add(stats, g.cluster, ST_TAU_ALG, c.tau);
-        stat_add(stats, g.cluster, ST_KICK, c.kick);
-        stat_add(stats, g.cluster, ST_DRIFT, c.drift);
-        stat_add(stats, g.cluster, ST_COMP, c.comp);
-        stat_add(stats, g.cluster, ST_SPLIT, c.split);
-        stat_add(stats, g.cluster, ST_KEPLER, c.kepler);
-        if (c.maxd >= 0) stat_max(stats, g.cluster, c.maxd);
-        fam_add(fam, 0, c.tau);
-        fam_add(fam, 1, c.kick);
+        if (g.cluster != cl) {
+            if (cl >= 0) pair_counters_flush(stats, fam, cl, tot);
+            tot = PairCounters{0, 0, 0, 0, 0, 0, -1};
+            cl = g.cluster;
+        }
+        tot.tau += c.tau;
+        tot.kick += c.kick;
+        tot.drift += c.drift;
+        tot.comp += c.comp;
+        tot.split += c.split;
+        tot.kepler += c.kepler;
+        tot.maxd = max(tot.maxd, c.maxd);
+    }
+    // the wavefront is whole again here
+    int cmax = cl;
+    for (int o = 32; o > 0; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o, 64));
+    if (__all(cl < 0 || cl == cmax)) {
+        if (cmax < 0) return;
+        PairCounters w;
+        w.tau = wave_sum_u64(tot.tau);
+        w.kick = wave_sum_u64(tot.kick);
+        w.drift = wave_sum_u64(tot.drift);
+        w.comp = wave_sum_u64(tot.comp);
+        w.split = wave_sum_u64(tot.split);
+        w.kepler = wave_sum_u64(tot.kepler);
+        int d = tot.maxd;
+        for (int o = 32; o > 0; o >>= 1) d = max(d, __shfl_xor(d, o, 64));
+        w.maxd = d;
+        if ((threadIdx.x & 63) == 0) pair_counters_flush(stats, fam, cmax, w);
+    } else if (cl >= 0) {
+        pair_counters_flush(stats, fam, cl, tot);
     }
 }
 
@@ -1290,6 +1371,7 @@ struct SmallKernel {
         for (int q = tid(); q < CAP; q += NT) L.cnt[q] = 0;
         sync();
         unsigned long long tau = 0;
+        bool over = false;  // an LDS union-find budget ran out
         const ScreenParams sq = screen_params(p, h);
         const ccs::Screen64 s64 = ccs::screen64_params(p.eta, h);
         const ccs::Far64 f64 = ccs::far64_params(p.eta, h);
@@ -1320,7 +1402,7 @@ struct SmallKernel {
                 const double r2 = ((dx * dx + dy * dy) + dz * dz) + p.eps2;
                 const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
                 if (ccs::far64(r2, v2, p.G * (ma + mb), f64)) continue;  // certainly no edge
-                if (edge_decide<MIXED>(dx, dy, dz, dvx, dvy, dvz, ma + mb, p, sq, s64, h)) lunite(L.par, a, b);
+                if (edge_decide<MIXED>(dx, dy, dz, dvx, dvy, dvz, ma + mb, p, sq, s64, h)) lunite(L.par, a, b, over);
             }
             tau += (unsigned long long)(e - a - 1);
         }
@@ -1330,10 +1412,11 @@ struct SmallKernel {
         for (int a = tid(); a < n; a += NT) {
             if (!is_main(L, a)) continue;
             const int s = L.segS[a];
-            const int lab = bit_of(L.flag, s) ? lfind(L.par, a) : s;
+            const int lab = bit_of(L.flag, s) ? lfind(L.par, a, over) : s;
             L.cid[a] = (int16_t)lab;
             atomicAdd(&L.cnt[lab], 1);
         }
+        if (over) atomicOr(&L.err, EB_BUDGET);
         sync();
         if (p.hold) hold_merge(L, n);
         scan_cnt(L);
@@ -1831,7 +1914,7 @@ hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, DevParam
 }
 
 hipError_t launch_sweep(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, DevParams p, double h,
-                        bool mixed, int split_tiles, bool star_pass, uint64_t *stats, uint64_t *fam, hipStream_t st)
+                        bool mixed, int split_tiles, bool star_pass, int32_t *err, hipStream_t st)
 {
     if (a.ntiles == 0) return hipSuccess;
     const int js = a.ntiles <= split_tiles ? 4 : 1;
@@ -1839,7 +1922,7 @@ hipError_t launch_sweep(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t
     const int nb = (a.ntiles + tpb - 1) / tpb;
 #define CC_SWEEP(M, J)                                                                                          \
     hipLaunchKernelGGL((k_sweep<M, J>), dim3(nb), dim3(TPB), 0, st, S, a.seg, a.tile_off, a.nseg, notstar, a.epoch, \
-                       star_pass ? 1 : 0, parent, p, h, stats, fam)
+                       star_pass ? 1 : 0, parent, p, h, err)
     if (mixed) {
         if (js == 4) CC_SWEEP(true, 4);
         else if (js == 2) CC_SWEEP(true, 2);
@@ -1854,11 +1937,12 @@ hipError_t launch_sweep(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t
 }
 
 hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,
-                        uint32_t *keys, uint32_t *vals, int32_t *count, int32_t *hold, uint64_t *stats,
-                        hipStream_t st)
+                        uint32_t *keys, uint32_t *vals, int32_t *count, int32_t *hold, bool star_pass,
+                        uint64_t *stats, uint64_t *sweep_fam, int32_t *err, hipStream_t st)
 {
     hipLaunchKernelGGL(k_label, dim3(a.nchunks), dim3(TPB), 0, st, a.seg, a.chunk_off, a.act_off, a.nseg, notstar,
-                       a.epoch, parent, label, cnt, keys, vals, count, hold, stats);
+                       a.epoch, parent, label, cnt, keys, vals, count, hold, star_pass ? 1 : 0, stats, sweep_fam,
+                       err);
     return hipGetLastError();
 }
 

@@ -54,17 +54,21 @@ hipError_t launch_uf_init(int32_t *parent, int32_t *cnt, int n, hipStream_t st);
 // screen32: FP32 screen in front of the FP64 one (the template flag MIXED of
 // the kernels' edge test); split_tiles: launches of at most this many tiles
 // take one block per tile
+// (the pairs it evaluates are counted by launch_label)
 hipError_t launch_sweep(SoA S, const GridLevelArgs &a, int32_t *notstar, int32_t *parent, DevParams p, double h,
-                        bool screen32, int split_tiles, bool star_pass, uint64_t *stats, uint64_t *fam, hipStream_t st);
+                        bool screen32, int split_tiles, bool star_pass, int32_t *err, hipStream_t st);
 // star test of every segment from its first slot (sets notstar for the
 // segments that are not fully connected)
 hipError_t launch_star(SoA S, const GridLevelArgs &a, int32_t *notstar, DevParams p, double h, bool screen32,
                        uint64_t *stats, uint64_t *fam, hipStream_t st);
 // labels and component sizes; with keys/vals the sort keys of the active
 // particles, with count the work-list counters cleared
+// Labels and component sizes after a sweep; also counts the pairs the sweep
+// evaluated (per segment: all of them, unless star_pass skipped a star set)
+// into stats and sweep_fam.
 hipError_t launch_label(const GridLevelArgs &a, const int32_t *notstar, int32_t *parent, int32_t *label, int32_t *cnt,
-                        uint32_t *keys, uint32_t *vals, int32_t *count, int32_t *hold, uint64_t *stats,
-                        hipStream_t st);
+                        uint32_t *keys, uint32_t *vals, int32_t *count, int32_t *hold, bool star_pass,
+                        uint64_t *stats, uint64_t *sweep_fam, int32_t *err, hipStream_t st);
 // HOLD split: merge the non-trivial components of every segment into one set
 // F (labels, sort keys and the size of F; hold: 2 ints per segment, prepared
 // by launch_label)

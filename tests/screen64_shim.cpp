@@ -42,3 +42,21 @@ extern "C" void far64_pairs(const double *x, const double *y, const double *z, c
         out[k] = ccs::far64(r2, v2, mu, ccs::far64_params(eta, h[k])) ? 1 : 0;
     }
 }
+
+// The sweep's form of the far-pair test: both particles checked against the
+// box once, r^2 and |u|^2 by fused multiply-adds, mu = G m_i + G m_j; a pair
+// outside the box is left to the screen (0).
+extern "C" void far64b_pairs(const double *x, const double *y, const double *z, const double *vx, const double *vy,
+                             const double *vz, const double *m, const int32_t *pi, const int32_t *pj, int64_t npairs,
+                             const double *h, double eta, double eps2, double G, int32_t *out)
+{
+    for (int64_t k = 0; k < npairs; ++k) {
+        const int i = pi[k], j = pj[k];
+        const double gi = G * m[i], gj = G * m[j];
+        const ccs::Far64 f = ccs::far64_params(eta, h[k]);
+        const bool box = f.on && eps2 <= 0x1p98 && ccs::far64_in_box(x[i], y[i], z[i], vx[i], vy[i], vz[i], gi) &&
+                         ccs::far64_in_box(x[j], y[j], z[j], vx[j], vy[j], vz[j], gj);
+        out[k] = (box && ccs::far64_boxed(x[i] - x[j], y[i] - y[j], z[i] - z[j], vx[i] - vx[j], vy[i] - vy[j],
+                                          vz[i] - vz[j], gi + gj, eps2, f)) ? 1 : 0;
+    }
+}

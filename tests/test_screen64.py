@@ -52,13 +52,18 @@ def _decide(shim, s, pi, pj, h, eta, eps2, G):
     return out
 
 
-def _far(shim, s, pi, pj, h, eta, eps2, G):
+# the far-pair test as the on-chip split calls it (far64), and in the sweep's
+# form (far64b: box check, fused multiply-adds, mu from the two G m)
+FAR_FORMS = ["far64_pairs", "far64b_pairs"]
+
+
+def _far(shim, s, pi, pj, h, eta, eps2, G, form="far64_pairs"):
     d = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))  # noqa: E731
     pi = np.ascontiguousarray(pi, np.int32)
     pj = np.ascontiguousarray(pj, np.int32)
     h = np.ascontiguousarray(h, np.float64)
     out = np.zeros(len(pi), np.int32)
-    shim.far64_pairs(d(s.x), d(s.y), d(s.z), d(s.vx), d(s.vy), d(s.vz), d(s.m),
+    getattr(shim, form)(d(s.x), d(s.y), d(s.z), d(s.vx), d(s.vy), d(s.vz), d(s.m),
                      pi.ctypes.data_as(C.POINTER(C.c_int32)), pj.ctypes.data_as(C.POINTER(C.c_int32)),
                      C.c_int64(len(pi)), d(h), C.c_double(eta), C.c_double(eps2), C.c_double(G),
                      out.ctypes.data_as(C.POINTER(C.c_int32)))
@@ -166,9 +171,10 @@ def _far_cases(rng, tau, n):
     }
 
 
+@pytest.mark.parametrize("form", FAR_FORMS)
 @pytest.mark.parametrize("eta,eps2,G", [(0.01, 0.0, 1.0), (0.3, 0.0, 1.0), (1.0, 1e-8, 4.3e-3),
                                          (0.003, 0.0, 1.0)])
-def test_far_test_never_contradicts_literal_test(shim, eta, eps2, G):
+def test_far_test_never_contradicts_literal_test(shim, eta, eps2, G, form):
     """Whenever the far-pair test certifies "no edge", the oracle's literal
     tau is >= h; far from the threshold it certifies most pairs."""
     rng = np.random.default_rng(9105 + int(eta * 1000))
@@ -179,17 +185,18 @@ def test_far_test_never_contradicts_literal_test(shim, eta, eps2, G):
     ok = (tau > 0) & np.isfinite(tau)
     for name, h in _far_cases(rng, tau, n).items():
         sel = ok & (h > 0) & np.isfinite(h)
-        far = _far(shim, s, pi[sel], pj[sel], h[sel], eta, eps2, G)
+        far = _far(shim, s, pi[sel], pj[sel], h[sel], eta, eps2, G, form)
         bad = far & (tau[sel] < h[sel])
         assert not bad.any(), f"{name}: {bad.sum()} pairs certified far with tau < h"
     # h well below every pair's tau: the test certifies the bulk of the pairs
     h = tau / 64.0
     sel = ok & (h >= 2.0 ** -60)
-    far = _far(shim, s, pi[sel], pj[sel], h[sel], eta, eps2, G)
+    far = _far(shim, s, pi[sel], pj[sel], h[sel], eta, eps2, G, form)
     assert far.mean() > 0.5, far.mean()
 
 
-def test_far_test_with_cut_margin_is_caught(shim_cut):
+@pytest.mark.parametrize("form", FAR_FORMS)
+def test_far_test_with_cut_margin_is_caught(shim_cut, form):
     """Planted mistake: the far-pair header built with its margin cut to one
     half certifies pairs whose tau lies just below h; the same cases find it.
     (The conditions are sufficient ones, tight only at corners of the input
@@ -203,12 +210,13 @@ def test_far_test_with_cut_margin_is_caught(shim_cut):
     wrong = 0
     for name, h in _far_cases(rng, tau, n).items():
         sel = ok & (h > 0) & np.isfinite(h)
-        far = _far(shim_cut, s, pi[sel], pj[sel], h[sel], 0.01, 0.0, 1.0)
+        far = _far(shim_cut, s, pi[sel], pj[sel], h[sel], 0.01, 0.0, 1.0, form)
         wrong += int((far & (tau[sel] < h[sel])).sum())
     assert wrong > 0
 
 
-def test_far_test_sweep_like_pairs(shim):
+@pytest.mark.parametrize("form", FAR_FORMS)
+def test_far_test_sweep_like_pairs(shim, form):
     """Pairs of a Plummer sphere at the pivot steps of the deep levels: the
     test agrees with the literal decision wherever it decides, and decides
     most pairs at small h."""
@@ -221,7 +229,7 @@ def test_far_test_sweep_like_pairs(shim):
     tau = oracle.pair_timesteps(s, pi, pj, p)
     for k in range(0, 12, 2):
         h = np.full(len(pi), 2.0 ** -(6 + k))
-        far = _far(shim, s, pi, pj, h, 0.01, 0.0, 1.0)
+        far = _far(shim, s, pi, pj, h, 0.01, 0.0, 1.0, form)
         assert not (far & (tau < h)).any(), k
         if k >= 6:
             assert far.mean() > 0.9, (k, far.mean())
