@@ -25,6 +25,11 @@ Beside the headline the line carries
     ratio at equal |dE/E| <= 1e-6;
   - `secondary`: the 16 384-body Salpeter Plummer workload, one global step
     at dt0 = 1/64 restarted from its initial conditions;
+  - `batching`: on that workload, the plain FP64 path (every set through the
+    grid-wide kernels) against the batched path in FP64 and in mixed
+    precision, wall seconds per N-body time at equal |dE/E| <= 1e-6;
+  - `paper_softened_plummer`: the paper's softened 1024-body Plummer test,
+    first global step, CC against HOLD (counts and time);
   - `cpu_baseline`: the FP64 CPU oracle on a bounded sample of the same state,
     on one host thread and on all host cores of this process.
 """
@@ -284,6 +289,89 @@ def secondary(dev, steps=3):
             "ms_per_step": (t1 - t0) * 1e3 / steps, "value": work / (t1 - t0), "unit": "pairs/s"}
 
 
+def batching(dev, etas=(0.005, 0.01, 0.02, 0.03), steps=4, bound=1e-6):
+    """The batched path against the plain one on the 16 384-body Salpeter
+    Plummer workload (dt0 = 1/64, `steps` global steps from its initial
+    conditions at each eta): plain FP64 (every set through the grid-wide
+    kernels, one level visit at a time), FP64 batched (two-body and small
+    components in persistent on-chip launches beside the recursion) and
+    mixed precision batched.  Each form's wall seconds per N-body time at the
+    largest eta whose |dE/E| <= bound, and the ratios."""
+    import torch
+
+    import synth
+    from paper_1407_7105_amd import CC_FP64, CC_MIXED, Context, State
+    wl = synth.WORKLOADS[2]
+    p = synth.workload(2)
+    dt0 = wl["dt"]
+    forms = (("plain_fp64", dict(plain=1, precision=CC_FP64)), ("batched_fp64", dict(precision=CC_FP64)),
+             ("batched_mixed", dict(precision=CC_MIXED)))
+    rows = []
+    for name, kw in forms:
+        for eta in etas:
+            ctx = Context(device=0, eta=eta, eps2=wl["eps2"], **kw)
+            s = State.from_numpy(p, device=dev)
+            e0 = ctx.diagnostics(s)["energy"]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = ctx.evolve(s, dt0, steps * dt0)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            e1 = ctx.diagnostics(s)["energy"]
+            ctx.close()
+            rows.append({"form": name, "eta": eta, "dE_over_E": abs((e1 - e0) / e0),
+                         "wall_s_per_nbody_time": wall / (steps * dt0), "splits": st["splits"],
+                         "max_depth_seen": st["max_depth_seen"]})
+            print(f"# batching {name} eta={eta}: |dE/E|={rows[-1]['dE_over_E']:.3e} "
+                  f"{rows[-1]['wall_s_per_nbody_time']:.3f} s per N-body time", file=sys.stderr, flush=True)
+    chosen = {}
+    for name, _ in forms:
+        ok = [r for r in rows if r["form"] == name and r["dE_over_E"] <= bound]
+        chosen[name] = max(ok, key=lambda r: r["eta"]) if ok else None
+
+    def ratio(a, b):
+        if chosen[a] and chosen[b]:
+            return chosen[a]["wall_s_per_nbody_time"] / chosen[b]["wall_s_per_nbody_time"]
+        return None
+    return {"workload": wl["name"], "n": p.n, "dt0": dt0, "t": steps * dt0, "bound": bound, "rows": rows,
+            "chosen": chosen, "mixed_batched_speedup_vs_plain_fp64": ratio("plain_fp64", "batched_mixed"),
+            "batched_fp64_speedup_vs_plain_fp64": ratio("plain_fp64", "batched_fp64")}
+
+
+def paper_splits(dev):
+    """The paper's softened Plummer test (Sec. 3.1): 1024 equal masses,
+    softening 1/256, eta = 0.01, the first global step of 700/512, under the
+    CC and HOLD splits: operation counts and GPU wall time of the step."""
+    import torch
+
+    import synth
+    from paper_1407_7105_amd import Context, State
+    p = synth.plummer(1024, 1)
+    dt = 700 / 512
+    out = {"n": 1024, "eps": 1 / 256, "eta": 0.01, "dt": dt,
+           "paper_cc_counts": {"kicks": 1.1e9, "tau_evals": 6.6e8, "drifts": 5.0e6}}
+    for name, hold in (("cc", 0), ("hold", 1)):
+        best = None
+        for _ in range(3):
+            ctx = Context(device=0, eta=0.01, eps2=(1 / 256) ** 2, hold=hold)
+            s = State.from_numpy(p, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = ctx.evolve(s, dt, dt)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ctx.close()
+            best = wall if best is None else min(best, wall)
+        out[name] = {"ms": best * 1e3, "tau_pairs_alg": st["tau_pairs_alg"], "kick_pairs": st["kick_pairs"],
+                     "kicks_both_sides": 2 * st["kick_pairs"], "drifts": st["drifts"],
+                     "max_depth_seen": st["max_depth_seen"]}
+        print(f"# paper softened Plummer first step, {name}: {best * 1e3:.1f} ms, {st['tau_pairs_alg']} tau, "
+              f"{2 * st['kick_pairs']} kicks, {st['drifts']} drifts", file=sys.stderr, flush=True)
+    out["hold_over_cc_time"] = out["hold"]["ms"] / out["cc"]["ms"]
+    out["hold_over_cc_tau"] = out["hold"]["tau_pairs_alg"] / out["cc"]["tau_pairs_alg"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -296,6 +384,8 @@ def main():
     ap.add_argument("--no-eta-scan", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-force-error", action="store_true")
+    ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--no-paper-splits", action="store_true")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the launch shapes on this workload first (the library defaults are the tuner's "
                          "choice on the 16 384-body workload)")
@@ -376,6 +466,8 @@ def main():
     ferr = None if args.no_force_error else mixed_force_error(p, wl, dev)
     scan = None if args.no_eta_scan else eta_scan(p, wl, dev, dt0)
     sec = None if args.no_secondary else secondary(dev)
+    bat = None if args.no_batching else batching(dev)
+    pap = None if args.no_paper_splits else paper_splits(dev)
 
     out = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
@@ -394,6 +486,8 @@ def main():
         "mixed_force_error": ferr,
         "eta_scan": scan,
         "secondary": sec,
+        "batching": bat,
+        "paper_softened_plummer": pap,
     }
     if base is not None:
         out["cpu_baseline"] = base

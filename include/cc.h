@@ -94,6 +94,12 @@ typedef struct {
                                below h, i.e. when it belongs to a non-trivial component; the
                                fast particles of a set are recursed into as ONE set F and every
                                pair with a slow member is kicked.  Not with kepler. */
+    int32_t plain;          /* 0: batched (default): two-body components, small components and
+                               all-small ensembles run in persistent on-chip launches beside the
+                               grid-wide recursion; 1: plain path, every set of two or more bodies
+                               is split and kicked by the grid-wide kernels, one level visit at a
+                               time (the reference for the batching comparison; small_max is
+                               ignored; not with kepler) */
 } cc_params;
 
 typedef struct {

@@ -34,7 +34,8 @@ class _State(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("eta", C.c_double), ("eps2", C.c_double), ("G", C.c_double), ("max_depth", C.c_int32),
                 ("precision", C.c_int32), ("small_max", C.c_int32), ("kick_order", C.c_int32),
-                ("screen", C.c_int32), ("kepler", C.c_int32), ("hold", C.c_int32)]
+                ("screen", C.c_int32), ("kepler", C.c_int32), ("hold", C.c_int32),
+                ("plain", C.c_int32)]
 
 
 class _Stats(C.Structure):
@@ -156,9 +157,9 @@ class Context:
     def __init__(self, device: int = 0, eta: float = 0.01, eps2: float = 0.0, G: float = 1.0,
                  max_depth: int = 48, precision: int = CC_FP64, small_max: int = 0,
                  kick_order: int = CC_ORDER_FAST, screen: int = CC_SCREEN_FP64, kepler: int = 0,
-                 hold: int = 0):
+                 hold: int = 0, plain: int = 0):
         self._L = load_library()
-        self._p = _Params(eta, eps2, G, max_depth, precision, small_max, kick_order, screen, kepler, hold)
+        self._p = _Params(eta, eps2, G, max_depth, precision, small_max, kick_order, screen, kepler, hold, plain)
         h = C.c_void_p()
         rc = self._L.cc_create(C.byref(h), device, C.byref(self._p))
         if rc != CC_OK:

@@ -174,7 +174,10 @@ DevParams dev_params(const cc_ctx *c)
     return p;
 }
 
-int small_max(const cc_ctx *c) { return c->params.small_max > 0 ? c->params.small_max : DEFAULT_SMALL_MAX; }
+// Largest set integrated on chip; 1 in plain mode, where every set of two or
+// more bodies takes the grid-wide kernels.
+int small_max_of(const cc_params &p) { return p.plain ? 1 : (p.small_max > 0 ? p.small_max : DEFAULT_SMALL_MAX); }
+int small_max(const cc_ctx *c) { return small_max_of(c->params); }
 
 bool mixed(const cc_ctx *c) { return c->params.precision == CC_MIXED; }
 
@@ -202,6 +205,9 @@ int check_params(cc_ctx *c, const cc_params *p)
         return fail(c, CC_ERR_ARG, "the Kepler solution of two-body components needs eps2 == 0");
     if (p->hold != 0 && p->hold != 1) return fail(c, CC_ERR_ARG, "hold must be 0 or 1");
     if (p->hold && p->kepler) return fail(c, CC_ERR_ARG, "the Kepler option belongs to the CC split, not to HOLD");
+    if (p->plain != 0 && p->plain != 1) return fail(c, CC_ERR_ARG, "plain must be 0 or 1");
+    if (p->plain && p->kepler)
+        return fail(c, CC_ERR_ARG, "the Kepler option runs in the on-chip pair walker, which plain mode leaves out");
     return CC_OK;
 }
 
@@ -1176,7 +1182,7 @@ int cc_set_params(cc_ctx *c, const cc_params *p)
     if (!c) return CC_ERR_ARG;
     c->err.clear();
     RC(check_params(c, p));
-    const bool sm_changed = small_max(c) != (p->small_max > 0 ? p->small_max : DEFAULT_SMALL_MAX);
+    const bool sm_changed = small_max(c) != small_max_of(*p);
     c->params = *p;
     if (sm_changed)
         for (auto &lv : c->levels) lv.cap_n = 0;
@@ -1333,7 +1339,8 @@ int cc_autotune(cc_ctx *c, const cc_state *s, int64_t n, double dt, cc_tune *out
         rc = fail(c, CC_ERR_DEVICE, "autotune events");
     const cc_params keep = c->params;
     const int32_t keep_split = c->sweep_split, keep_kg = c->kick_groups;
-    cc_tune best{small_max(c), c->sweep_split, c->kick_groups, 1e300, 0};
+    // (in plain mode nothing runs on chip: the on-chip size limit is not tuned)
+    cc_tune best{keep.plain ? keep.small_max : small_max(c), c->sweep_split, c->kick_groups, 1e300, 0};
     // one untimed step (buffers sized for the setting), then the best of two
     auto time_step = [&](double *ms_out) -> int {
         float best_ms = 1e30f;
@@ -1365,7 +1372,7 @@ int cc_autotune(cc_ctx *c, const cc_state *s, int64_t n, double dt, cc_tune *out
     const int32_t sm_cand[] = {64, 128, 256, 512};
     const int32_t split_cand[] = {0, 512, 2048, 8192};
     const int32_t kg_cand[] = {2, 4, 8, 16};
-    for (int knob = 0; knob < 3 && rc == CC_OK; ++knob) {
+    for (int knob = keep.plain ? 1 : 0; knob < 3 && rc == CC_OK; ++knob) {
         const int32_t *cand = knob == 0 ? sm_cand : knob == 1 ? split_cand : kg_cand;
         cc_tune base = best;
         for (int i = 0; i < 4 && rc == CC_OK; ++i) {

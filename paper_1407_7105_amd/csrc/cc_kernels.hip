@@ -698,7 +698,7 @@ __global__ __launch_bounds__(TPB) void k_permute(SoA from, SoA to, const Seg *__
                         fam_add(kick_fam, 1, (uint64_t)0 - in);
                     }
                     const Seg c = {dst, size, g.cluster, g.depth + 1};
-                    if (size == 2) {
+                    if (size == 2 && L.small_max >= 2) {
                         const int i = atomicAdd(&L.count[0], 1);
                         if (i < L.cap_pairs) L.pairs[i] = c;
                     } else if (size <= L.small_max) {
