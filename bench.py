@@ -289,7 +289,7 @@ def secondary(dev, steps=3):
             "ms_per_step": (t1 - t0) * 1e3 / steps, "value": work / (t1 - t0), "unit": "pairs/s"}
 
 
-def batching(dev, etas=(0.005, 0.01, 0.02, 0.03), steps=4, bound=1e-6):
+def batching(dev, etas=(0.01, 0.03, 0.1, 0.3), steps=4, bound=1e-6):
     """The batched path against the plain one on the 16 384-body Salpeter
     Plummer workload (dt0 = 1/64, `steps` global steps from its initial
     conditions at each eta): plain FP64 (every set through the grid-wide

@@ -827,13 +827,20 @@ __global__ __launch_bounds__(TPB) void k_kick_seg(SoA W, const Seg *__restrict__
 // tile in list order, so the result is deterministic.  The pairs kicked are
 // counted by the forward permutation (n(n-1)/2 per segment less s(s-1)/2 per
 // component), not here.
+// A partner of the tiled kick: position and G m.
+struct alignas(16) KickPartner {
+    double x, y, z, gm;
+};
+
 template <bool MIXED>
 __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict__ seg,
                                                      const KickBlock *__restrict__ blk,
                                                      const int32_t *__restrict__ labp, double eps2, double G,
                                                      double *__restrict__ part, int32_t *err)
 {
-    __shared__ double jx[TPB], jy[TPB], jz[TPB], jm[TPB];
+    // the block's partners, 256 at a time: one 32-byte record each (G m in
+    // FP32 precision for the mixed kick), read by all lanes at once
+    __shared__ KickPartner kj[TPB];
     __shared__ int32_t jl[TPB];
     const KickBlock kb = blk[blockIdx.x];
     const Seg g = seg[kb.seg];
@@ -848,65 +855,51 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
     const int32_t iu = (labp[ifirst] == labp[ilast]) ? labp[ifirst] : -1;
     double ax = 0.0, ay = 0.0, az = 0.0;
     bool ok = true;
-    if (!MIXED) {
-        // FP64: every wavefront reads the partners through the scalar cache
-        // into scalar registers (the kernel writes none of x, y, z, m, labp),
-        // four at a time, so the partner loop costs no LDS bandwidth and no
-        // barrier.  No branch per partner: partners of the own component add
-        // a zero factor; a coincident pair shows as a non-finite sum.
-        for (int jb = jlo; jb < jhi; jb += TPB) {
-            const int jn = min(TPB, jhi - jb);
-            const int jfirst = g.start + jb, jlast = g.start + jb + jn - 1;
-            if (iu >= 0 && labp[jfirst] == iu && labp[jlast] == iu) continue;  // uniform across the block
-            const int base = __builtin_amdgcn_readfirstlane(jfirst);
-            const int jnu = __builtin_amdgcn_readfirstlane(jn);
-            const CDouble *cx = to_const(W.x) + base, *cy = to_const(W.y) + base, *cz = to_const(W.z) + base;
-            const CDouble *cm = to_const(W.m) + base;
-            const CInt *cl = to_const(labp) + base;
-            int jj = 0;
-            for (; jj + 4 <= jnu; jj += 4) {
-                double X[4], Y[4], Z[4], M[4];
-                int32_t Lb[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    X[k] = cx[jj + k]; Y[k] = cy[jj + k]; Z[k] = cz[jj + k]; M[k] = cm[jj + k]; Lb[k] = cl[jj + k];
-                }
-#pragma unroll
-                for (int k = 0; k < 4; ++k)
-                    accel_term_rsq_if(Lb[k] != li, xi, yi, zi, X[k], Y[k], Z[k], G * M[k], eps2, ax, ay, az);
-            }
-            for (; jj < jnu; ++jj)
-                accel_term_rsq_if(cl[jj] != li, xi, yi, zi, cx[jj], cy[jj], cz[jj], G * cm[jj], eps2, ax, ay, az);
-        }
-    }
-    for (int jb = jlo; MIXED && jb < jhi; jb += TPB) {
+    for (int jb = jlo; jb < jhi; jb += TPB) {
         const int jn = min(TPB, jhi - jb);
         const int jfirst = g.start + jb, jlast = g.start + jb + jn - 1;
         if (iu >= 0 && labp[jfirst] == iu && labp[jlast] == iu) continue;  // uniform across the block
         __syncthreads();
         if (threadIdx.x < jn) {
             const int j = g.start + jb + threadIdx.x;
-            jx[threadIdx.x] = W.x[j];
-            jy[threadIdx.x] = W.y[j];
-            jz[threadIdx.x] = W.z[j];
-            jm[threadIdx.x] = MIXED ? (double)(float)(G * W.m[j]) : G * W.m[j];
+            KickPartner q;
+            q.x = W.x[j];
+            q.y = W.y[j];
+            q.z = W.z[j];
+            q.gm = MIXED ? (double)(float)(G * W.m[j]) : G * W.m[j];
+            kj[threadIdx.x] = q;
             jl[threadIdx.x] = labp[j];
         }
         __syncthreads();
-        if (valid) {
-            if (MIXED) {
-                // FP32 forces on FP64 differences, Kahan-compensated within the
-                // tile, FP64 across tiles
-                Kahan3 k{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-                const float e2 = (float)eps2;
-                for (int jj = 0; jj < jn; ++jj) {
-                    if (jl[jj] == li) continue;
-                    ok &= accel_term32(xi, yi, zi, jx[jj], jy[jj], jz[jj], (float)jm[jj], e2, k);
+        const int jnu = __builtin_amdgcn_readfirstlane(jn);
+        if (!MIXED) {
+            // FP64, no branch per partner: partners of the own component add a
+            // zero factor; a coincident pair shows as a non-finite sum
+            int jj = 0;
+            for (; jj + 4 <= jnu; jj += 4) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const KickPartner q = kj[jj + k];
+                    accel_term_rsq_if(jl[jj + k] != li, xi, yi, zi, q.x, q.y, q.z, q.gm, eps2, ax, ay, az);
                 }
-                ax += (double)k.sx - (double)k.cx;
-                ay += (double)k.sy - (double)k.cy;
-                az += (double)k.sz - (double)k.cz;
             }
+            for (; jj < jnu; ++jj) {
+                const KickPartner q = kj[jj];
+                accel_term_rsq_if(jl[jj] != li, xi, yi, zi, q.x, q.y, q.z, q.gm, eps2, ax, ay, az);
+            }
+        } else if (valid) {
+            // FP32 forces on FP64 differences, Kahan-compensated within the
+            // tile, FP64 across tiles
+            Kahan3 k{0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+            const float e2 = (float)eps2;
+            for (int jj = 0; jj < jnu; ++jj) {
+                if (jl[jj] == li) continue;
+                const KickPartner q = kj[jj];
+                ok &= accel_term32(xi, yi, zi, q.x, q.y, q.z, (float)q.gm, e2, k);
+            }
+            ax += (double)k.sx - (double)k.cx;
+            ay += (double)k.sy - (double)k.cy;
+            az += (double)k.sz - (double)k.cz;
         }
     }
     double *pb = part + (size_t)blockIdx.x * 3 * TPB;
