@@ -372,6 +372,69 @@ def paper_splits(dev):
     return out
 
 
+def _run(dev, p, dt0, t_end, **kw):
+    """One integration from p's state: (|dE/E|, wall s, stats)."""
+    import torch
+
+    from paper_1407_7105_amd import Context, State
+    ctx = Context(device=0, **kw)
+    s = State.from_numpy(p, device=dev)
+    e0 = ctx.diagnostics(s)["energy"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.evolve(s, dt0, t_end)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    e1 = ctx.diagnostics(s)["energy"]
+    ctx.close()
+    return abs((e1 - e0) / e0), wall, st
+
+
+def repro_eta_scan(dev, etas=(0.003, 0.01, 0.03, 0.1), dt0=1 / 64, t_end=1.0):
+    """The paper's second-order test (Sec. 3.1): the softened 1024-body
+    Plummer sphere (softening 1/256) for one N-body time at several eta under
+    the CC and HOLD splits: |dE/E| (second order in eta) and GPU wall time."""
+    import synth
+    p = synth.plummer(1024, 1)
+    rows = []
+    for name, hold in (("cc", 0), ("hold", 1)):
+        for eta in etas:
+            de, wall, st = _run(dev, p, dt0, t_end, eta=eta, eps2=(1 / 256) ** 2, hold=hold)
+            rows.append({"split": name, "eta": eta, "dE_over_E": de, "wall_s": wall,
+                         "tau_pairs_alg": st["tau_pairs_alg"], "kick_pairs": st["kick_pairs"]})
+            print(f"# repro eta scan {name} eta={eta}: |dE/E|={de:.3e} {wall:.3f} s", file=sys.stderr, flush=True)
+    slopes = {}
+    for name in ("cc", "hold"):
+        r = [x for x in rows if x["split"] == name]
+        slopes[name] = [float(np.log(r[k + 1]["dE_over_E"] / r[k]["dE_over_E"]) / np.log(r[k + 1]["eta"] / r[k]["eta"]))
+                        for k in range(len(r) - 1)]
+    return {"n": 1024, "eps": 1 / 256, "dt0": dt0, "t": t_end, "rows": rows, "slopes": slopes}
+
+
+def repro_fractal(dev, dims=(1.6, 2.0, 2.6, 3.0), seeds=(1, 2, 3, 4), dt0=1 / 64, t_end=0.25, eta=0.03):
+    """The paper's fractal test (Sec. 3.3): 1024 equal-mass bodies in
+    Goodwin-Whitworth box fractals of dimension D, virial ratio 1/2, no
+    softening, eta = 0.03, integrated for 1/4 N-body time under CC, CC_KEPLER
+    and HOLD: mean |dE/E|, GPU wall time and pair steps over the seeds."""
+    import synth
+    rows = []
+    for dim in dims:
+        ps = [synth.fractal(1024, 100 * int(10 * dim) + sd, dim=dim) for sd in seeds]
+        for name, kw in (("cc", {}), ("cc_kepler", {"kepler": 1}), ("hold", {"hold": 1})):
+            des, walls, taus = [], [], []
+            for p in ps:
+                de, wall, st = _run(dev, p, dt0, t_end, eta=eta, **kw)
+                des.append(de)
+                walls.append(wall)
+                taus.append(st["tau_pairs_alg"])
+            rows.append({"dim": dim, "method": name, "dE_over_E_mean": float(np.mean(des)),
+                         "wall_s_mean": float(np.mean(walls)), "tau_pairs_alg_mean": float(np.mean(taus))})
+            print(f"# repro fractal D={dim} {name}: |dE/E|={rows[-1]['dE_over_E_mean']:.3e} "
+                  f"{rows[-1]['wall_s_mean']:.3f} s {rows[-1]['tau_pairs_alg_mean']:.3e} tau", file=sys.stderr,
+                  flush=True)
+    return {"n": 1024, "eta": eta, "dt0": dt0, "t": t_end, "seeds": list(seeds), "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -386,6 +449,8 @@ def main():
     ap.add_argument("--no-force-error", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
     ap.add_argument("--no-paper-splits", action="store_true")
+    ap.add_argument("--repro", action="store_true",
+                    help="also run the paper's eta scan (Sec. 3.1) and fractal-dimension scan (Sec. 3.3) on the GPU")
     ap.add_argument("--autotune", action="store_true",
                     help="tune the launch shapes on this workload first (the library defaults are the tuner's "
                          "choice on the 16 384-body workload)")
@@ -468,6 +533,7 @@ def main():
     sec = None if args.no_secondary else secondary(dev)
     bat = None if args.no_batching else batching(dev)
     pap = None if args.no_paper_splits else paper_splits(dev)
+    rep = {"eta_scan": repro_eta_scan(dev), "fractal": repro_fractal(dev)} if args.repro else None
 
     out = {
         "metric": METRIC, "value": value, "unit": "pairs/s", "n_gpus": 1,
@@ -489,6 +555,8 @@ def main():
         "batching": bat,
         "paper_softened_plummer": pap,
     }
+    if rep is not None:
+        out["repro"] = rep
     if base is not None:
         out["cpu_baseline"] = base
     print(json.dumps(out), flush=True)
