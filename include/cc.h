@@ -211,7 +211,7 @@ int cc_diagnostics(cc_ctx *ctx, const cc_state *s, int64_t n, double *out, void 
  * runs on a copy) while it varies, one at a time from the best so far, the
  * largest component run on chip (small_max in {64, 128, 256, 512}), the sweep
  * launches that give each tile a whole workgroup (up to {0, 512, 2048, 8192}
- * tiles) and the kick blocks per compute unit ({2, 4, 8, 16}); keeps the
+ * tiles) and the kick blocks per compute unit ({8, 16, 32, 64}); keeps the
  * fastest in the context (params.small_max is overwritten) and reports it in
  * *out (may be NULL).  Partitions and results in the EXACT kick order do not
  * depend on the choice.  Allocates a copy of the state; syncs. */

@@ -36,7 +36,7 @@ constexpr int DEFAULT_SMALL_MAX = 128;  // the autotuner's choice on the 16 384-
 constexpr int kLevels = 64;  // grid recursion levels a context can hold (max_depth <= 60)
 constexpr int SWEEP_TILE = 64;  // edge of the all-pairs sweep tiles
 constexpr int32_t DEFAULT_SWEEP_SPLIT = 2048;
-constexpr int32_t DEFAULT_KICK_GROUPS = 4;
+constexpr int32_t DEFAULT_KICK_GROUPS = 32;
 
 // kernel families for timing
 enum Fam { F_SWEEP, F_LABEL, F_SORT, F_PERMUTE, F_DRIFT, F_KICK, F_PAIRS, F_SMALL, F_VALIDATE, F_OTHER, F_N };
@@ -1371,7 +1371,7 @@ int cc_autotune(cc_ctx *c, const cc_state *s, int64_t n, double dt, cc_tune *out
     // coordinate descent over the three shapes, each from the best so far
     const int32_t sm_cand[] = {64, 128, 256, 512};
     const int32_t split_cand[] = {0, 512, 2048, 8192};
-    const int32_t kg_cand[] = {2, 4, 8, 16};
+    const int32_t kg_cand[] = {8, 16, 32, 64};
     for (int knob = keep.plain ? 1 : 0; knob < 3 && rc == CC_OK; ++knob) {
         const int32_t *cand = knob == 0 ? sm_cand : knob == 1 ? split_cand : kg_cand;
         cc_tune base = best;

@@ -234,7 +234,7 @@ def test_autotune_reads_only_and_keeps_exact_results():
     g = State.from_numpy(s)
     t = ctx.autotune(g, 1 / 64)
     assert t["small_max"] in (64, 128, 256, 512) and t["sweep_split_tiles"] in (0, 512, 2048, 8192)
-    assert t["kick_groups_per_cu"] in (2, 4, 8, 16)
+    assert t["kick_groups_per_cu"] in (8, 16, 32, 64)
     assert t["trials"] == 12 and t["ms_per_step"] > 0
     assert_state_equal(g.to_numpy(), s, "autotune input")
     ref = s.copy()
