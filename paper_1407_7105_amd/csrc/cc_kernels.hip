@@ -833,7 +833,7 @@ struct alignas(16) KickPartner {
 };
 
 template <bool MIXED>
-__global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict__ seg,
+__global__ __launch_bounds__(TPB, 8) void k_kick_tiles(SoA W, const Seg *__restrict__ seg,
                                                      const KickBlock *__restrict__ blk,
                                                      const int32_t *__restrict__ labp, double eps2, double G,
                                                      double *__restrict__ part, int32_t *err)
@@ -873,19 +873,37 @@ __global__ __launch_bounds__(TPB) void k_kick_tiles(SoA W, const Seg *__restrict
         __syncthreads();
         const int jnu = __builtin_amdgcn_readfirstlane(jn);
         if (!MIXED) {
-            // FP64, no branch per partner: partners of the own component add a
-            // zero factor; a coincident pair shows as a non-finite sum
+            // FP64, no branch per partner; a coincident pair shows as a
+            // non-finite sum.  Labels are non-decreasing along a segment, so a
+            // chunk whose label range misses the i tile's holds no partner of
+            // an own component (nor i itself): no mask at all.  Otherwise
+            // partners of the own component add a zero factor.
+            const bool disjoint = labp[jlast] < labp[ifirst] || labp[jfirst] > labp[ilast];  // uniform
             int jj = 0;
-            for (; jj + 4 <= jnu; jj += 4) {
+            if (disjoint) {
+                for (; jj + 4 <= jnu; jj += 4) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const KickPartner q = kj[jj + k];
-                    accel_term_rsq_if(jl[jj + k] != li, xi, yi, zi, q.x, q.y, q.z, q.gm, eps2, ax, ay, az);
+                    for (int k = 0; k < 4; ++k) {
+                        const KickPartner q = kj[jj + k];
+                        accel_term_rsq_if(true, xi, yi, zi, q.x, q.y, q.z, q.gm, eps2, ax, ay, az);
+                    }
                 }
-            }
-            for (; jj < jnu; ++jj) {
-                const KickPartner q = kj[jj];
-                accel_term_rsq_if(jl[jj] != li, xi, yi, zi, q.x, q.y, q.z, q.gm, eps2, ax, ay, az);
+                for (; jj < jnu; ++jj) {
+                    const KickPartner q = kj[jj];
+                    accel_term_rsq_if(true, xi, yi, zi, q.x, q.y, q.z, q.gm, eps2, ax, ay, az);
+                }
+            } else {
+                for (; jj + 4 <= jnu; jj += 4) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const KickPartner q = kj[jj + k];
+                        accel_term_rsq_if(jl[jj + k] != li, xi, yi, zi, q.x, q.y, q.z, q.gm, eps2, ax, ay, az);
+                    }
+                }
+                for (; jj < jnu; ++jj) {
+                    const KickPartner q = kj[jj];
+                    accel_term_rsq_if(jl[jj] != li, xi, yi, zi, q.x, q.y, q.z, q.gm, eps2, ax, ay, az);
+                }
             }
         } else if (valid) {
             // FP32 forces on FP64 differences, Kahan-compensated within the
