@@ -34,6 +34,10 @@ namespace {
 constexpr int TPB = 256;
 constexpr int DEFAULT_SMALL_MAX = 128;  // the autotuner's choice on the 16 384-body workload
 constexpr int kLevels = 64;  // grid recursion levels a context can hold (max_depth <= 60)
+#ifndef CC_SIDE_STREAMS
+#define CC_SIDE_STREAMS 3
+#endif
+constexpr int kSide = CC_SIDE_STREAMS;  // side streams for the on-chip launches (with the main one: 4 hardware queues)
 constexpr int SWEEP_TILE = 64;  // edge of the all-pairs sweep tiles
 constexpr int32_t DEFAULT_SWEEP_SPLIT = 2048;
 constexpr int32_t DEFAULT_KICK_GROUPS = 32;
@@ -94,7 +98,10 @@ struct cc_ctx {
     cc_params params{};
     std::string err;
     hipStream_t st = nullptr;
-    hipStream_t side = nullptr;  // default priority: a level's on-chip components beside the recursion
+    // default priority: a level's on-chip components beside the recursion,
+    // level k on side[k % kSide] (a deeper level's launch need not queue
+    // behind a long launch of a shallower one)
+    hipStream_t side[kSide] = {};
     std::vector<hipEvent_t> sync_pool;     // ordering events (no timing)
     std::vector<hipEvent_t> sync_used;
     int cus = 256;
@@ -403,7 +410,7 @@ void flush_timing(cc_ctx *c)
 {
     if (c->recs.empty()) return;
     hipStreamSynchronize(c->st);
-    hipStreamSynchronize(c->side);
+    for (auto sd : c->side) hipStreamSynchronize(sd);
     for (auto &r : c->recs) {
         float ms = 0.f;
         hipEventElapsedTime(&ms, r.a, r.b);
@@ -597,7 +604,7 @@ int upload_kick_list(cc_ctx *c, Level &lv, const std::vector<Seg> &segs, const s
     if (bytes > lv.cap_kick || nslot > c->kick_part_cap) {
         // buffers still read by queued kicks: let both streams drain first
         HIPCHK(hipStreamSynchronize(c->st));
-        HIPCHK(hipStreamSynchronize(c->side));
+        for (auto sd : c->side) HIPCHK(hipStreamSynchronize(sd));
         if (bytes > lv.cap_kick) {
             const size_t cap = std::max(bytes, 2 * lv.cap_kick);
             RC(dalloc(c, &lv.kick, cap));
@@ -664,11 +671,12 @@ int dispatch_sets(cc_ctx *c, int k, Level &lv, double H, const std::vector<Seg> 
         if (!big.empty()) RC(evolve_grid(c, k + 1, big, H, big_desc, big_tot));
         return CC_OK;
     }
-    RC(order_streams(c, c->st, c->side));
-    RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, c->side, k + 1));
+    hipStream_t sd = c->side[k % kSide];
+    RC(order_streams(c, c->st, sd));
+    RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, sd, k + 1));
     hipEvent_t done;
     RC(take_event(c, &done));
-    HIPCHK(hipEventRecord(done, c->side));
+    HIPCHK(hipEventRecord(done, sd));
     RC(evolve_grid(c, k + 1, big, H, big_desc, big_tot));
     HIPCHK(hipStreamWaitEvent(c->st, done, 0));
     return CC_OK;
@@ -932,7 +940,7 @@ int evolve_on_chip_graph(cc_ctx *c, const std::vector<Seg> &top, int64_t n, int6
     const int mode = mixed(c) ? 2 : (exact_order(c) ? 1 : 0);
     HIPCHK(configure_items(small_max(c), mode));
     const size_t bytes = (size_t)n * sizeof(double);
-    hipStream_t g = c->side;
+    hipStream_t g = c->side[0];
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     HIPCHK(hipStreamBeginCapture(g, hipStreamCaptureModeThreadLocal));
@@ -1050,7 +1058,7 @@ int evolve_common(cc_ctx *c, cc_state *s, int64_t n, const int64_t *off, int32_t
             if (*c->h_err) rc = err_code(c, *c->h_err);
         }
         if (rc != CC_OK) {
-            hipStreamSynchronize(c->side);
+            for (auto sd : c->side) hipStreamSynchronize(sd);
             hipStreamSynchronize(c->st);
             recycle_sync_events(c);
             for (int a = 0; a < 6; ++a)
@@ -1123,10 +1131,13 @@ int cc_create(cc_ctx **out, int32_t hip_device, const cc_params *p)
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
         c->cus = cus;
     // default priority, no implicit synchronisation with the null stream
-    if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
-        delete c;
-        return CC_ERR_DEVICE;
-    }
+    for (auto &sd : c->side)
+        if (hipStreamCreateWithFlags(&sd, hipStreamNonBlocking) != hipSuccess) {
+            for (auto q : c->side)
+                if (q) hipStreamDestroy(q);
+            delete c;
+            return CC_ERR_DEVICE;
+        }
     if (dalloc(c, &c->errf, 1) != CC_OK || halloc(c, &c->h_err, 1) != CC_OK || dalloc(c, &c->qhead, 4 * kLevels) != CC_OK ||
         dalloc(c, &c->diag_out, 16) != CC_OK || halloc(c, &c->h_diag, 16) != CC_OK ||
         dalloc(c, &c->fam_work, 2 * F_N) != CC_OK) {
@@ -1173,7 +1184,8 @@ void cc_destroy(cc_ctx *c)
     for (auto e : c->ev_pool) hipEventDestroy(e);
     for (auto e : c->sync_pool) hipEventDestroy(e);
     for (auto e : c->sync_used) hipEventDestroy(e);
-    if (c->side) hipStreamDestroy(c->side);
+    for (auto sd : c->side)
+        if (sd) hipStreamDestroy(sd);
     delete c;
 }
 
