@@ -48,7 +48,8 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 METRIC = "pair interactions/s; wall-s per N-body time, FP64 vs mixed @ same |dE/E|"
-FLOP_TAU = 48      # FP64 operations of one pair time step, eq. 19 (div and sqrt counted as 1)
+FLOP_TAU = 54      # FP64 operations of one literal pair time step, eq. 19: 44 + 7 divisions + 3 roots
+                   # (division and root counted as 1)
 FLOP_KICK = 26     # FP64 operations of one symmetric pair kick, eqs. 8-9
 PEAK_FP64_VECTOR = 78.6e12   # MI355X: 256 CU x 2.4 GHz x 128 FP64 FLOP/clk/CU
 
@@ -57,12 +58,17 @@ DT0 = 1.0 / 512
 
 # HBM bytes per sweep launch on this workload and step (rocprofv3 FETCH_SIZE
 # x 2.0 + WRITE_SIZE x 1.0, the factors from a plain 256 MiB device copy; see
-# profiles/hbm_traffic_plummer262k_salpeter_bin10_fp64.md), valid for the
-# kernel sources with this SHA-1 only: any other source reports null.
-SWEEP_TRAFFIC_BYTES = None
+# profiles/hbm_traffic_plummer262k_salpeter_bin10_fp64.md) and the sweep's
+# counter-measured FP64 rate (profiles/counters_plummer262k_salpeter_bin10_fp64.md),
+# valid for the kernel sources with this SHA-1 only: any other source reports null.
+SWEEP_TRAFFIC_BYTES = 3.42e9
+SWEEP_COUNTERS = {"fp64_flop_per_pair": 29.9, "valu_instructions_per_pair": 39.5, "valu_issue": 0.85,
+                  "achieved_tflops": 25.1, "frac": 25.1 / 78.6,
+                  "note": "FP64 add, mul, trans x1 and FMA x2 from SQ_INSTS_VALU_*_F64 x 64 lanes, one step"}
 SWEEP_TRAFFIC_SOURCES = ("paper_1407_7105_amd/csrc/cc_kernels.hip", "paper_1407_7105_amd/csrc/cc_device.h",
-                         "paper_1407_7105_amd/csrc/cc_screen64.h")
-SWEEP_TRAFFIC_SHA1 = None
+                         "paper_1407_7105_amd/csrc/cc_screen64.h", "paper_1407_7105_amd/csrc/cc_screen32.h",
+                         "paper_1407_7105_amd/csrc/cc_tiles.h", "paper_1407_7105_amd/csrc/cc_kepler.h")
+SWEEP_TRAFFIC_SHA1 = "cda6491bbc13ad26bb981fd401baf69bca47ef69"
 
 
 def sources_sha1():
@@ -78,6 +84,10 @@ def sweep_traffic():
     if SWEEP_TRAFFIC_BYTES is None:
         return None
     return SWEEP_TRAFFIC_BYTES if sources_sha1() == SWEEP_TRAFFIC_SHA1 else None
+
+
+def sweep_counters():
+    return SWEEP_COUNTERS if sources_sha1() == SWEEP_TRAFFIC_SHA1 else None
 
 
 def cpu_model() -> str:
@@ -525,6 +535,8 @@ def main():
     cons["t"] = (args.warmup + args.steps) * dt0
 
     roof = roofline_of(fam, "sweep", FLOP_TAU, 0, sweep_traffic())
+    if roof is not None:
+        roof["counter_measured"] = sweep_counters()
     roof_kick = roofline_of(fam, "kick", 0, FLOP_KICK)
     ctx.close()
 
