@@ -297,6 +297,19 @@ constexpr int ST = 64;  // sweep tile edge (one wavefront)
 #define FAR_UNROLL 4
 #endif
 
+// Workgroups of a launch are handed to the eight XCDs in turn (block b to XCD
+// b mod 8), and each XCD has its own L2.  The sweep renumbers its blocks so
+// that every XCD takes one contiguous share of the tile order: with the
+// blocked tile order, consecutive tiles share their particles, which then
+// stay in that XCD's L2.  A bijection of [0, nb).
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb)
+{
+    const int q = nb / NXCD, r = nb % NXCD;
+    const int x = b % NXCD, k = b / NXCD;
+    return x * q + min(x, r) + k;
+}
+
 // A partner of the sweep's far-pair loop, with G m for the test's mu.
 struct alignas(16) Partner {
     double x, y, z, m, vx, vy, vz, gm;
@@ -330,7 +343,7 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
     __shared__ uint32_t eflag[TPW][2 * ST / 32];  // slots of the tile that carry an edge
     const int w = threadIdx.x / ST, lane = threadIdx.x % ST;
     const int ts = w / JS, jpart = w % JS;
-    const int tile = blockIdx.x * TPW + ts;
+    const int tile = xcd_block(blockIdx.x, gridDim.x) * TPW + ts;
     const int total = tile_off[nseg];
     int s = 0, ti = 0, tj = 0, T = 0;
     bool active = tile < total;
@@ -342,7 +355,7 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
     if (active) {
         g = seg[s];
         T = (g.n + ST - 1) / ST;
-        cct::tri_tile(T, tile - tile_off[s], ti, tj);
+        cct::blocked_tile(T, tile - tile_off[s], ti, tj);
     }
     const bool diag = (ti == tj);
     const int jn = active ? min(ST, g.n - tj * ST) : 0;

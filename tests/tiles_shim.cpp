@@ -14,3 +14,14 @@ extern "C" void tri_tiles(int T, int64_t t0, int64_t count, int32_t *out)
         out[2 * k + 1] = tj;
     }
 }
+
+// The same in the blocked order.
+extern "C" void blocked_tiles(int T, int64_t t0, int64_t count, int32_t *out)
+{
+    for (int64_t k = 0; k < count; ++k) {
+        int ti, tj;
+        cct::blocked_tile(T, (int)(t0 + k), ti, tj);
+        out[2 * k] = ti;
+        out[2 * k + 1] = tj;
+    }
+}
