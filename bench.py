@@ -25,6 +25,8 @@ Beside the headline the line carries
     ratio at equal |dE/E| <= 1e-6;
   - `secondary`: the 16 384-body Salpeter Plummer workload, one global step
     at dt0 = 1/64 restarted from its initial conditions;
+  - `cc_kepler`: the headline workload with two-body components advanced by
+    the Kepler flow (CC_KEPLER), same work measure;
   - `batching`: on that workload, the plain FP64 path (every set through the
     grid-wide kernels) against the batched path in FP64 and in mixed
     precision, wall seconds per N-body time at equal |dE/E| <= 1e-6;
@@ -299,6 +301,36 @@ def secondary(dev, steps=3):
             "ms_per_step": (t1 - t0) * 1e3 / steps, "value": work / (t1 - t0), "unit": "pairs/s"}
 
 
+def kepler_leg(p, wl, dev, dt0, steps=3):
+    """CC_KEPLER (two-body components by the Kepler flow) on the headline
+    workload: one warm-up and `steps` timed global steps from the initial
+    conditions, the same work measure as the headline."""
+    import torch
+
+    from paper_1407_7105_amd import Context, State
+    ctx = Context(device=0, eta=wl["eta"], eps2=wl["eps2"], kepler=1)
+    s = State.from_numpy(p, device=dev)
+    d0 = ctx.diagnostics(s)
+    ctx.evolve(s, dt0, dt0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    work = solves = 0
+    for _ in range(steps):
+        st = ctx.evolve(s, dt0, dt0)
+        work += st["tau_pairs_alg"] + st["kick_pairs"]
+        solves += st["kepler_solves"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    d1 = ctx.diagnostics(s)
+    ctx.close()
+    cons = conservation(d0, d1, p)
+    cons["t"] = (steps + 1) * dt0
+    print(f"# cc_kepler: {wall * 1e3 / steps:.1f} ms per step, |dE/E| {cons['dE_over_E']:.3e}", file=sys.stderr,
+          flush=True)
+    return {"ms_per_step": wall * 1e3 / steps, "value": work / wall, "unit": "pairs/s",
+            "kepler_solves_per_step": solves / steps, "conservation": cons}
+
+
 def batching(dev, etas=(0.01, 0.03, 0.1, 0.3), steps=4, bound=1e-6):
     """The batched path against the plain one on the 16 384-body Salpeter
     Plummer workload (dt0 = 1/64, `steps` global steps from its initial
@@ -458,6 +490,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-force-error", action="store_true")
     ap.add_argument("--no-batching", action="store_true")
+    ap.add_argument("--no-kepler", action="store_true")
     ap.add_argument("--no-paper-splits", action="store_true")
     ap.add_argument("--repro", action="store_true",
                     help="also run the paper's eta scan (Sec. 3.1) and fractal-dimension scan (Sec. 3.3) on the GPU")
@@ -543,6 +576,7 @@ def main():
     ferr = None if args.no_force_error else mixed_force_error(p, wl, dev)
     scan = None if args.no_eta_scan else eta_scan(p, wl, dev, dt0)
     sec = None if args.no_secondary else secondary(dev)
+    kep = None if args.no_kepler else kepler_leg(p, wl, dev, dt0)
     bat = None if args.no_batching else batching(dev)
     pap = None if args.no_paper_splits else paper_splits(dev)
     rep = {"eta_scan": repro_eta_scan(dev), "fractal": repro_fractal(dev)} if args.repro else None
@@ -564,6 +598,7 @@ def main():
         "mixed_force_error": ferr,
         "eta_scan": scan,
         "secondary": sec,
+        "cc_kepler": kep,
         "batching": bat,
         "paper_softened_plummer": pap,
     }

@@ -792,6 +792,51 @@ def test_ensemble_full_size_sampled_clusters_bitwise():
             assert sts[c][k] == ost[k], (c, k, sts[c][k], ost[k])
 
 
+def test_ensemble_mixed_to_t1_against_oracle_runs():
+    """Sampled clusters of the 1024-cluster ensemble (clusters 16-20 bodies with
+    20% binaries, whose FP64 oracle runs take seconds) integrated together in
+    mixed precision to t = 1, 64 global steps of one batch each.  Small chaotic
+    clusters with hard binaries diverge from any other run within a few
+    steps, so each is compared with its own oracle run by what survives: an
+    energy error of the same order (within 10x, or below 1e-5, the mixed
+    kick's own level over 64 steps), momenta conserved to the mixed kick's
+    rounding, and the same deepest recursion level within two."""
+    s = synth.workload(4)
+    picks = (889, 984, 828, 85)
+    parts = [Particles(*(getattr(s, f)[s.offsets[c]:s.offsets[c + 1]].copy()
+                         for f in ("x", "y", "z", "vx", "vy", "vz", "m"))) for c in picks]
+    sizes = [q.n for q in parts]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    cat = Particles.from_arrays(np.concatenate([q.pos() for q in parts]), np.concatenate([q.vel() for q in parts]),
+                                np.concatenate([q.m for q in parts]))
+    p = oracle.Params(eta=0.01)
+    g = State.from_numpy(cat)
+    ctx = ctx_for(p, kick_order=CC_ORDER_FAST, precision=CC_MIXED)
+    maxd = [0] * len(picks)
+    for step in range(64):
+        sts = ctx.evolve_batch(g, off, 1 / 64, 1 / 64)
+        maxd = [max(a, st["max_depth_seen"]) for a, st in zip(maxd, sts)]
+        if step % 16 == 15:
+            print(f"mixed ensemble clusters {picks}: {step + 1} of 64 steps", flush=True)
+    got = g.to_numpy()
+    for k, c in enumerate(picks):
+        a, b = off[k], off[k + 1]
+        init = parts[k]
+        mine = Particles(*([got[f][a:b].copy() for f in ("x", "y", "z", "vx", "vy", "vz")] + [init.m.copy()]))
+        ref = init.copy()
+        _, ost = oracle.evolve(ref, 1 / 64, 1.0, p)
+        print(f"oracle run of cluster {c} done", flush=True)
+        d0, dg, do = oracle.diagnostics(init), oracle.diagnostics(mine), oracle.diagnostics(ref)
+        eg = abs(dg["energy"] / d0["energy"] - 1)
+        eo = abs(do["energy"] / d0["energy"] - 1)
+        assert eg <= max(10 * eo, 1e-5), (c, eg, eo)
+        pscale = np.sum(init.m * np.linalg.norm(init.vel(), axis=1))
+        lscale = np.sum(init.m * np.linalg.norm(np.cross(init.pos(), init.vel()), axis=1))
+        assert np.linalg.norm(dg["P"] - d0["P"]) <= 1e-6 * pscale, c
+        assert np.linalg.norm(dg["L"] - d0["L"]) <= 1e-6 * lscale, c
+        assert abs(maxd[k] - ost["max_depth_seen"]) <= 2, (c, maxd[k], ost["max_depth_seen"])
+
+
 # ------------------------------------------------------------------ CC_KEPLER
 
 STAT_KEYS_K = STAT_KEYS + ("kepler_solves",)
