@@ -353,12 +353,45 @@ __device__ inline bool kepler_pair_dev(Body &a, Body &b, double h, double G)
     return true;
 }
 
+// The FP64 screen's h-independent terms for the current state of a pair
+// (differences a - b, as edge_decide forms them).
+__device__ __forceinline__ ccs::Screen64Pair pair_screen(const Body &a, const Body &b, double msum,
+                                                         const DevParams &p)
+{
+    const double dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    const double dvx = a.vx - b.vx, dvy = a.vy - b.vy, dvz = a.vz - b.vz;
+    const double r2 = ((dx * dx + dy * dy) + dz * dz) + p.eps2;
+    const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
+    const double rv = (dx * dvx + dy * dvy) + dz * dvz;
+    return ccs::screen64_pair(r2, v2, rv, p.G * msum, p.eta);
+}
+
+// edge_decide for the walker: in FP64 the screen's verdict at h from the
+// terms `sp` kept for the state, the literal formula for what it leaves open.
+template <bool MIXED>
+__device__ __forceinline__ bool pair_decide(const Body &a, const Body &b, double msum, const ccs::Screen64Pair &sp,
+                                            const DevParams &p, double h)
+{
+    if (MIXED)
+        return edge_decide<true>(a.x - b.x, a.y - b.y, a.z - b.z, a.vx - b.vx, a.vy - b.vy, a.vz - b.vz, msum, p,
+                                 screen_params(p, h), ccs::screen64_params(p.eta, h), h);
+    const int sc = ccs::screen64_at(sp, ccs::screen64_params(p.eta, h));
+    if (sc != ccs::SCREEN64_UNSURE) return sc == ccs::SCREEN64_EDGE;
+    return edge_pair(a.x - b.x, a.y - b.y, a.z - b.z, a.vx - b.vx, a.vy - b.vy, a.vz - b.vz, msum, p, h);
+}
+
 // Returns 0, or EB_DEPTH / EB_BUDGET / EB_NONFINITE (a and b are then partly
 // advanced; the caller discards them: a failing global step is restored from
 // its snapshot).  With CC_KEPLER (p.kepler), a pair that is a component
 // found by a split (`component`) is advanced by the Kepler flow for H; a
 // top-level two-particle set is split first, and once its two particles form
 // a component each half of it is one Kepler flow of h/2.
+//   One walk is a sequence of dependent steps in one lane, so its length is
+// set by the instructions per node: the state only changes at a leaf (or a
+// Kepler step), so the FP64 screen's h-independent terms are formed once per
+// state and reused by the decisions of a descent; the counters are kept per
+// walk (decisions, decisions that found an edge, leaves) and added at the end;
+// and the levels whose second half has ended are left in one step.
 template <bool MIXED>
 __device__ inline int evolve_pair(Body &a, Body &b, double H, int32_t depth0, const DevParams &p,
                                   PairCounters &c, bool component = false)
@@ -367,34 +400,46 @@ __device__ inline int evolve_pair(Body &a, Body &b, double H, int32_t depth0, co
         c.kepler++;
         return kepler_pair_dev(a, b, H, p.G) ? 0 : EB_NONFINITE;
     }
-    uint64_t second = 0;
-    uint64_t leaves = 0;
-    int lvl = 0;
+    if (depth0 > p.max_depth) return EB_DEPTH;
+    uint64_t second = 0;  // bit l set while level l runs its second half
+    uint32_t nd = 0, ne = 0, nl = 0;
+    int lvl = 0, maxlvl = 0, rc = 0;
     double h = H;
     const double msum = a.m + b.m;
+    ccs::Screen64Pair sp{};
+    bool fresh = true;  // the state changed since sp was formed
     for (;;) {
-        const int32_t depth = depth0 + lvl;
-        if (depth > p.max_depth) return EB_DEPTH;
-        if (depth > c.maxd) c.maxd = depth;
-        c.split++;
-        c.tau++;
-        const bool e = edge_decide<MIXED>(a.x - b.x, a.y - b.y, a.z - b.z, a.vx - b.vx, a.vy - b.vy,
-                                          a.vz - b.vz, msum, p, screen_params(p, h),
-                                          ccs::screen64_params(p.eta, h), h);
+        ++nd;
+        if (!MIXED && fresh) {
+            sp = pair_screen(a, b, msum, p);
+            fresh = false;
+        }
+        const bool e = pair_decide<MIXED>(a, b, msum, sp, p, h);
         if (e && p.kepler) {
             // the pair is a component at h: its two halves are Kepler flows of h/2
-            c.comp++;
-            c.kepler += 2;
-            if (!kepler_pair_dev(a, b, 0.5 * h, p.G) || !kepler_pair_dev(a, b, 0.5 * h, p.G)) return EB_NONFINITE;
+            ++ne;
+            if (!kepler_pair_dev(a, b, 0.5 * h, p.G) || !kepler_pair_dev(a, b, 0.5 * h, p.G)) {
+                rc = EB_NONFINITE;
+                break;
+            }
+            fresh = true;
         } else if (e) {
-            if (lvl >= 63) return EB_DEPTH;  // deeper than the walker can track: treat as the depth cap
-            c.comp++;
-            lvl++;
+            // deeper than the walker can track, or than max_depth
+            if (lvl >= 63 || depth0 + lvl + 1 > p.max_depth) {
+                rc = EB_DEPTH;
+                break;
+            }
+            ++ne;
+            ++lvl;
+            maxlvl = max(maxlvl, lvl);
             h = 0.5 * h;
             second &= ~(1ull << lvl);
             continue;
         } else {
-            if (++leaves > PAIR_LEAF_BUDGET) return EB_BUDGET;
+            if (++nl > PAIR_LEAF_BUDGET) {
+                rc = EB_BUDGET;
+                break;
+            }
             // leaf: D_{h/2} K_h D_{h/2} on two singletons
             const double hh = 0.5 * h;
             a.x += hh * a.vx; a.y += hh * a.vy; a.z += hh * a.vz;
@@ -412,18 +457,26 @@ __device__ inline int evolve_pair(Body &a, Body &b, double H, int32_t depth0, co
             b.vx += h * bax; b.vy += h * bay; b.vz += h * baz;
             a.x += hh * a.vx; a.y += hh * a.vy; a.z += hh * a.vz;
             b.x += hh * b.vx; b.y += hh * b.vy; b.z += hh * b.vz;
-            c.kick++;
-            c.drift += 4;
+            fresh = true;
         }
-        // advance to the next sibling
-        while (lvl > 0 && ((second >> lvl) & 1ull)) {
-            second &= ~(1ull << lvl);
-            lvl--;
-            h = 2.0 * h;
-        }
-        if (lvl == 0) return 0;
-        second |= (1ull << lvl);
+        // advance to the next sibling: the levels lvl, lvl-1, ... whose second
+        // half has just ended are left, and the deepest level l <= lvl still
+        // in its first half starts its second half (the walk ends if none is)
+        const uint64_t open = ~second & (((2ull << lvl) - 1ull) & ~1ull);
+        if (open == 0) break;
+        const int l = 63 - __builtin_clzll(open);
+        second = (second & ((2ull << l) - 1ull)) | (1ull << l);
+        h = ldexp(H, -l);
+        lvl = l;
     }
+    c.split += nd;
+    c.tau += nd;
+    c.comp += ne;
+    c.kick += nl;
+    c.drift += 4ull * nl;
+    if (p.kepler) c.kepler += 2ull * ne;
+    if (depth0 + maxlvl > c.maxd) c.maxd = depth0 + maxlvl;
+    return rc;
 }
 
 }  // namespace ccg
