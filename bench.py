@@ -63,14 +63,14 @@ DT0 = 1.0 / 512
 # profiles/hbm_traffic_plummer262k_salpeter_bin10_fp64.md) and the sweep's
 # counter-measured FP64 rate (profiles/counters_plummer262k_salpeter_bin10_fp64.md),
 # valid for the kernel sources with this SHA-1 only: any other source reports null.
-SWEEP_TRAFFIC_BYTES = 5.26e8
+SWEEP_TRAFFIC_BYTES = 5.28e8
 SWEEP_COUNTERS = {"fp64_flop_per_pair": 29.4, "valu_instructions_per_pair": 41.0, "valu_issue": 0.86,
-                  "achieved_tflops": 24.1, "frac": 24.1 / 78.6,
+                  "achieved_tflops": 24.2, "frac": 24.2 / 78.6,
                   "note": "FP64 add, mul, trans x1 and FMA x2 from SQ_INSTS_VALU_*_F64 x 64 lanes, one step"}
 SWEEP_TRAFFIC_SOURCES = ("paper_1407_7105_amd/csrc/cc_kernels.hip", "paper_1407_7105_amd/csrc/cc_device.h",
                          "paper_1407_7105_amd/csrc/cc_screen64.h", "paper_1407_7105_amd/csrc/cc_screen32.h",
                          "paper_1407_7105_amd/csrc/cc_tiles.h", "paper_1407_7105_amd/csrc/cc_kepler.h")
-SWEEP_TRAFFIC_SHA1 = "032a906b9e5be9b3a9f7fb1d80c4467ace4dcb4d"
+SWEEP_TRAFFIC_SHA1 = "0ac55558f33280ea98ff89db4bd4bb1e71bfe371"
 
 
 def sources_sha1():
