@@ -129,6 +129,17 @@ struct cc_ctx {
     double *kick_part = nullptr; // partial accelerations of the tiled kick
     size_t kick_part_cap = 0;    // in kick blocks
     std::vector<int32_t> kick_scratch;  // host scratch of the kick-list builder
+    // A level's on-chip launch waiting for its child level's first sweep to
+    // be queued (see dispatch_sets)
+    struct Deferred {
+        bool on = false;
+        int k = 0;
+        double H = 0.0;
+        int n_pairs = 0;
+        int n_small[4] = {0, 0, 0, 0};
+        hipStream_t sd = nullptr;
+        hipEvent_t done = nullptr;
+    } deferred;
     double *diag_part = nullptr;
     size_t diag_cap = 0;
     double *diag_out = nullptr, *h_diag = nullptr;
@@ -534,6 +545,7 @@ int run_small_and_pairs(cc_ctx *c, int k, Level &lv, double H, int n_pairs, cons
 
 int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h,
                 const unsigned char *pre_desc = nullptr, const DescTotals *pre_tot = nullptr);
+int launch_deferred(cc_ctx *c);
 
 // Kick blocks of one level visit, in the component-contiguous order: every
 // 256-slot i tile sees its whole segment, except that a tile lying inside one
@@ -671,14 +683,44 @@ int dispatch_sets(cc_ctx *c, int k, Level &lv, double H, const std::vector<Seg> 
         if (!big.empty()) RC(evolve_grid(c, k + 1, big, H, big_desc, big_tot));
         return CC_OK;
     }
+    // The launch goes to a side stream once the child level's first sweep is
+    // queued on the main stream (launch_deferred, called by evolve_grid after
+    // that sweep): started together, its blocks took the compute units'
+    // registers while that sweep began, which slowed the sweep, and the
+    // launch is not needed before this level's kick, after the whole child
+    // recursion.
     hipStream_t sd = c->side[k % kSide];
     RC(order_streams(c, c->st, sd));
-    RC(run_small_and_pairs(c, k, lv, H, n_pairs, n_small, sd, k + 1));
-    hipEvent_t done;
-    RC(take_event(c, &done));
-    HIPCHK(hipEventRecord(done, sd));
-    RC(evolve_grid(c, k + 1, big, H, big_desc, big_tot));
+    auto &d = c->deferred;
+    d.on = true;
+    d.k = k;
+    d.H = H;
+    d.n_pairs = n_pairs;
+    for (int b = 0; b < 4; ++b) d.n_small[b] = n_small[b];
+    d.sd = sd;
+    RC(take_event(c, &d.done));
+    hipEvent_t done = d.done;
+    const int rc = evolve_grid(c, k + 1, big, H, big_desc, big_tot);
+    if (c->deferred.on) {
+        // the child queued no sweep: launch now, or drop it after an error
+        if (rc != CC_OK) c->deferred.on = false;
+        else RC(launch_deferred(c));
+    }
+    RC(rc);
     HIPCHK(hipStreamWaitEvent(c->st, done, 0));
+    return CC_OK;
+}
+
+// The pending on-chip launch of dispatch_sets, on its side stream after the
+// work queued on the main stream so far (the child level's sweep).
+int launch_deferred(cc_ctx *c)
+{
+    auto &d = c->deferred;
+    if (!d.on) return CC_OK;
+    d.on = false;
+    RC(order_streams(c, c->st, d.sd));
+    RC(run_small_and_pairs(c, d.k, c->levels[d.k], d.H, d.n_pairs, d.n_small, d.sd, d.k + 1));
+    HIPCHK(hipEventRecord(d.done, d.sd));
     return CC_OK;
 }
 
@@ -729,6 +771,7 @@ int evolve_grid(cc_ctx *c, int k, const std::vector<Seg> &segs, double h, const 
         HIPCHK(launch_sweep(W, a, lv.notstar, c->parent, p, h, screen32(c), c->sweep_split, star_pass, c->errf,
                             c->st));
     }
+    RC(launch_deferred(c));
     {
         Span s(c, F_LABEL);
         const bool hold = c->params.hold != 0;
