@@ -60,6 +60,42 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t v)
     return v;
 }
 
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Inclusive prefix sum over the lanes of a wavefront.
+__device__ __forceinline__ int wave_incl_scan_i32(int v)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Position of the k-th (0-based) set bit of m (k < popcount(m)).
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int k)
+{
+    int pos = 0;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const uint64_t low = m & ((1ull << w) - 1ull);
+        const int c = __popcll(low);
+        if (k >= c) {
+            k -= c;
+            m >>= w;
+            pos += w;
+        } else {
+            m = low;
+        }
+    }
+    return pos;
+}
+
 // Block-wide sum to thread 0 (TPB threads).
 __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t *sh)
 {
@@ -338,8 +374,10 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
     // each wavefront's partners: one 64-byte record per partner, read by all
     // lanes at once (a broadcast) in the far-pair loop
     __shared__ Partner pj[NW][JW];
-    __shared__ int32_t lpar[TPW][2 * ST];
-    __shared__ int32_t groot[TPW][2 * ST];
+    // lpar and groot also hold the wavefront's edge and undecided bits during
+    // a cooperative stage two (JS = 1: one wavefront per tile)
+    __shared__ __align__(16) int32_t lpar[TPW][2 * ST];
+    __shared__ __align__(16) int32_t groot[TPW][2 * ST];
     __shared__ uint32_t eflag[TPW][2 * ST / 32];  // slots of the tile that carry an edge
     const int w = threadIdx.x / ST, lane = threadIdx.x % ST;
     const int ts = w / JS, jpart = w % JS;
@@ -367,16 +405,7 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
     int32_t *lp = lpar[ts];
     int32_t *gr = groot[ts];
     uint32_t *ef = eflag[ts];
-    if (jpart == 0) {
-        lp[lane] = lane;
-        gr[lane] = -1;
-        if (lane < 2 * ST / 32) ef[lane] = 0;
-    }
-    if (lane < JW) {
-        const int v = ST + j0w + lane;
-        lp[v] = v;
-        gr[v] = -1;
-    }
+    if (jpart == 0 && lane < 2 * ST / 32) ef[lane] = 0;
     // this wavefront's partners, and whether they and its own particles all
     // lie in the far-pair test's box
     bool inbox = true;
@@ -448,8 +477,64 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
         const int sh = lane + 1 - j0w;  // first partner bit with j > i
         const uint64_t keep = !ivalid ? 0ull : (!diag || sh <= 0) ? ~0ull : (sh >= 64) ? 0ull : (~0ull << sh);
         smask &= keep;
-        // Stage two, each lane over its own open pairs: the certified screen.
+        // Stage two: the certified screen on the open pairs.  Each lane takes
+        // its own, unless a few lanes hold most of them (near the top pivot
+        // steps, where many pairs lie close to the threshold): then the
+        // wavefront deals them out 64 at a time, each lane screening the k-th
+        // open pair of the wavefront for its owner lane, and the verdicts go
+        // back to the owners through LDS (this tile's lpar and groot, not yet
+        // in use).  Both ways screen the same pairs with the same arguments.
         uint64_t umask = 0;
+        const int nopen = __popcll(smask);
+        bool coop = false;
+        if (JS == 1) {
+            const int cmax = wave_max_i32(nopen);
+            if (cmax > 4) {
+                const int incl = wave_incl_scan_i32(nopen);
+                const int total = __shfl(incl, 63, 64);
+                const int rounds = (total + 63) / 64;
+                coop = cmax > 2 * rounds + 2;  // uniform across the wavefront
+                if (coop) {
+                    uint64_t *em = reinterpret_cast<uint64_t *>(lp);  // 64 words each
+                    uint64_t *um = reinterpret_cast<uint64_t *>(gr);
+                    em[lane] = 0;
+                    um[lane] = 0;
+                    const int excl = incl - nopen;
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    for (int base = 0; base < total; base += 64) {
+                        const int t = base + lane;
+                        // owner: the last lane whose first open pair is at or before t
+                        int o = 0;
+#pragma unroll
+                        for (int stp = 32; stp >= 1; stp >>= 1) {
+                            const int ex = __shfl(excl, o + stp, 64);
+                            if (o + stp < 64 && ex <= t) o += stp;
+                        }
+                        const int ko = t - __shfl(excl, o, 64);
+                        const uint64_t mo = __shfl(smask, o, 64);
+                        if (t < total) {
+                            const int jj = nth_set_bit(mo, ko);
+                            const int io = g.start + ti * ST + o;
+                            const Partner &r = P[jj];
+                            const int d = edge_screen<MIXED>(S.x[io] - r.x, S.y[io] - r.y, S.z[io] - r.z,
+                                                             S.vx[io] - r.vx, S.vy[io] - r.vy, S.vz[io] - r.vz,
+                                                             S.m[io] + r.m, p, q, s64);
+                            const uint64_t bit = 1ull << jj;
+                            if (d == ccs::SCREEN64_EDGE) atomicOr(&em[o], bit);
+                            if (d == ccs::SCREEN64_UNSURE) atomicOr(&um[o], bit);
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    emask = em[lane];
+                    umask = um[lane];
+                    smask = 0;
+                }
+            }
+        }
         while (smask) {
             const int jj = __builtin_ctzll(smask);
             smask &= smask - 1;
@@ -475,12 +560,23 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
         // flag the slots that carry an edge: this lane's particle, and every
         // partner some lane links to
         if (emask) atomicOr(&ef[lane >> 5], 1u << (lane & 31));
-        const uint64_t any = wave_or_u64(emask);
+        const uint64_t any = wave_or_u64(emask);  // (also orders the LDS reads above before the reset below)
         if (lane == 0 && any) {
             const int base = (diag ? 0 : ST) + j0w;  // slot of partner bit 0 (a multiple of JW)
             atomicOr(&ef[base >> 5], (uint32_t)(any << (base & 31)));
             if (JW > 32) atomicOr(&ef[(base >> 5) + 1], (uint32_t)(any >> 32));
         }
+    }
+    // the tile-local union-find over its 2 ST slots (after a cooperative
+    // stage two, which used this memory)
+    if (jpart == 0) {
+        lp[lane] = lane;
+        gr[lane] = -1;
+    }
+    if (lane < JW) {
+        const int v = ST + j0w + lane;
+        lp[v] = v;
+        gr[v] = -1;
     }
     __syncthreads();
     // global roots of the flagged slots only: a tile without an edge (most
