@@ -129,6 +129,30 @@ def test_mixed_split_wide_dynamic_range():
 
 
 @pytest.mark.parametrize("precision", [CC_FP64, CC_MIXED])
+def test_split_clump_many_open_pairs_in_few_lanes(precision):
+    """A dense clump of 1000 bodies scattered through the slots of 6000,
+    split at thresholds among the clump's own pair steps: the clump's lanes
+    hold many undecided pairs and the others none, so the sweep deals the
+    open pairs out over the wavefront (more than 2048 tiles: one wavefront
+    per tile).  Labels bit-identical to the oracle's."""
+    rng = np.random.default_rng(4099)
+    n, nc = 6000, 1000
+    pos = rng.normal(size=(n, 3))
+    vel = rng.normal(size=(n, 3)) * 0.5
+    clump = rng.choice(n, nc, replace=False)
+    pos[clump] = 1e-3 * rng.normal(size=(nc, 3))
+    vel[clump] = 0.05 * rng.normal(size=(nc, 3))
+    s = Particles.from_arrays(pos, vel, np.full(n, 1.0 / n))
+    p = oracle.Params(eta=0.01)
+    ci, cj = rng.choice(clump, 4000), rng.choice(clump, 4000)
+    keep = ci != cj
+    tau = oracle.pair_timesteps(s, ci[keep].astype(np.int32), cj[keep].astype(np.int32), p)
+    # from many small components to one holding the whole clump
+    for q in (0.0005, 0.002, 0.01, 0.2, 0.8):
+        check_split(s, float(np.quantile(tau, q)), p, precision=precision)
+
+
+@pytest.mark.parametrize("precision", [CC_FP64, CC_MIXED])
 @pytest.mark.parametrize("cfg,h", [(1, 1 / 64), (1, 1 / 1024), (2, 1 / 64), (2, 1 / 4096)])
 def test_split_workloads(cfg, h, precision):
     s = synth.workload(cfg)
