@@ -487,7 +487,7 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
         uint64_t umask = 0;
         const int nopen = __popcll(smask);
         bool coop = false;
-        if (JS == 1) {
+        if (JS == 1 && !MIXED) {  // (with the FP32 screen in front, the registers spill)
             const int cmax = wave_max_i32(nopen);
             if (cmax > 4) {
                 const int incl = wave_incl_scan_i32(nopen);
@@ -535,12 +535,18 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
                 }
             }
         }
+        // this lane's particle again for stages two and three (a cached
+        // load: kept in registers through the cooperative stage two, it spilled)
+        const double xs = __builtin_nontemporal_load(&S.x[i]), ys = __builtin_nontemporal_load(&S.y[i]),
+                     zs = __builtin_nontemporal_load(&S.z[i]), vxs = __builtin_nontemporal_load(&S.vx[i]),
+                     vys = __builtin_nontemporal_load(&S.vy[i]), vzs = __builtin_nontemporal_load(&S.vz[i]),
+                     ms = __builtin_nontemporal_load(&S.m[i]);
         while (smask) {
             const int jj = __builtin_ctzll(smask);
             smask &= smask - 1;
             const Partner &r = P[jj];
-            const int d = edge_screen<MIXED>(xi - r.x, yi - r.y, zi - r.z, vxi - r.vx, vyi - r.vy, vzi - r.vz,
-                                             mi + r.m, p, q, s64);
+            const int d = edge_screen<MIXED>(xs - r.x, ys - r.y, zs - r.z, vxs - r.vx, vys - r.vy, vzs - r.vz,
+                                             ms + r.m, p, q, s64);
             const uint64_t bit = 1ull << jj;
             emask |= (d == ccs::SCREEN64_EDGE) ? bit : 0ull;
             umask |= (d == ccs::SCREEN64_UNSURE) ? bit : 0ull;
@@ -549,7 +555,7 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
             const int jj = __builtin_ctzll(umask);
             umask &= umask - 1;
             const Partner &r = P[jj];
-            if (edge_pair(xi - r.x, yi - r.y, zi - r.z, vxi - r.vx, vyi - r.vy, vzi - r.vz, mi + r.m, p, h))
+            if (edge_pair(xs - r.x, ys - r.y, zs - r.z, vxs - r.vx, vys - r.vy, vzs - r.vz, ms + r.m, p, h))
                 emask |= 1ull << jj;
         }
         if (ti == 0 && lane == 0) {

@@ -132,9 +132,10 @@ def test_mixed_split_wide_dynamic_range():
 def test_split_clump_many_open_pairs_in_few_lanes(precision):
     """A dense clump of 1000 bodies scattered through the slots of 6000,
     split at thresholds among the clump's own pair steps: the clump's lanes
-    hold many undecided pairs and the others none, so the sweep deals the
-    open pairs out over the wavefront (more than 2048 tiles: one wavefront
-    per tile).  Labels bit-identical to the oracle's."""
+    hold many undecided pairs and the others none, so in FP64 the sweep
+    deals the open pairs out over the wavefront (more than 2048 tiles: one
+    wavefront per tile; mixed precision keeps them per lane).  Labels
+    bit-identical to the oracle's."""
     rng = np.random.default_rng(4099)
     n, nc = 6000, 1000
     pos = rng.normal(size=(n, 3))
