@@ -445,9 +445,11 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
         // literal formula), then resolve the undecided pairs and link the
         // edges.  Stage one, uniform across the wavefront: the far-pair test
         // on r^2, |u|^2 and mu, which settles most pairs of the deep levels;
-        // partners are broadcast from LDS, eight per step, and their bits
-        // gathered eight at a time.  Outside the test's box (never for
-        // particles of a star cluster) every pair stays open.
+        // partners are broadcast from LDS, FAR_UNROLL per step.  Each test's
+        // verdict stays a wavefront mask (the lanes with an open pair against
+        // that partner, scalar registers); only a step that left some pair
+        // open moves its bits into the lanes' masks.  Outside the test's box
+        // (never for particles of a star cluster) every pair stays open.
         const Partner *P = pj[w];
         const int jnu = __builtin_amdgcn_readfirstlane(jnw);
         uint64_t smask = jnu >= 64 ? ~0ull : ((1ull << jnu) - 1ull);
@@ -456,15 +458,21 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
             smask = 0;
             int j0 = 0;
             for (; j0 + FAR_UNROLL <= jnu; j0 += FAR_UNROLL) {
-                uint32_t c = 0;
+                uint64_t open[FAR_UNROLL];
+                uint64_t any = 0;
 #pragma unroll
                 for (int k = 0; k < FAR_UNROLL; ++k) {
                     const Partner r = P[j0 + k];
-                    const bool far = ccs::far64_boxed(xi - r.x, yi - r.y, zi - r.z, vxi - r.vx, vyi - r.vy,
-                                                      vzi - r.vz, gmi + r.gm, eps2, f64);
-                    c |= far ? 0u : (1u << k);
+                    const ccs::Far64Terms t = ccs::far64_boxed_terms(xi - r.x, yi - r.y, zi - r.z, vxi - r.vx,
+                                                                     vyi - r.vy, vzi - r.vz, gmi + r.gm, eps2, f64);
+                    open[k] = ~(__ballot(t.r2ok) & __ballot(t.ff) & __ballot(t.fb1) &
+                                (__ballot(t.fb2) | __ballot(t.still)));
+                    any |= open[k];
                 }
-                smask |= (uint64_t)c << j0;
+                if (any) {
+#pragma unroll
+                    for (int k = 0; k < FAR_UNROLL; ++k) smask |= ((open[k] >> lane) & 1ull) << (j0 + k);
+                }
             }
             for (; j0 < jnu; ++j0) {
                 const Partner r = P[j0];
