@@ -381,7 +381,9 @@ __global__ __launch_bounds__(TPB, SWEEP_WAVES) void k_sweep(SoA S, const Seg *__
     __shared__ uint32_t eflag[TPW][2 * ST / 32];  // slots of the tile that carry an edge
     const int w = threadIdx.x / ST, lane = threadIdx.x % ST;
     const int ts = w / JS, jpart = w % JS;
-    const int tile = xcd_block(blockIdx.x, gridDim.x) * TPW + ts;
+    // one tile per wavefront: its index, decode and segment are wavefront-
+    // uniform and go to the scalar unit
+    const int tile = __builtin_amdgcn_readfirstlane(xcd_block(blockIdx.x, gridDim.x) * TPW + ts);
     const int total = tile_off[nseg];
     int s = 0, ti = 0, tj = 0, T = 0;
     bool active = tile < total;
