@@ -63,14 +63,14 @@ DT0 = 1.0 / 512
 # profiles/hbm_traffic_plummer262k_salpeter_bin10_fp64.md) and the sweep's
 # counter-measured FP64 rate (profiles/counters_plummer262k_salpeter_bin10_fp64.md),
 # valid for the kernel sources with this SHA-1 only: any other source reports null.
-SWEEP_TRAFFIC_BYTES = 5.26e8
-SWEEP_COUNTERS = {"fp64_flop_per_pair": 27.6, "valu_instructions_per_pair": 37.3, "valu_issue": 0.84,
-                  "achieved_tflops": 24.4, "frac": 24.4 / 78.6,
+SWEEP_TRAFFIC_BYTES = 5.28e8
+SWEEP_COUNTERS = {"fp64_flop_per_pair": 27.6, "valu_instructions_per_pair": 34.6, "valu_issue": 0.83,
+                  "achieved_tflops": 25.9, "frac": 25.9 / 78.6,
                   "note": "FP64 add, mul, trans x1 and FMA x2 from SQ_INSTS_VALU_*_F64 x 64 lanes, one step"}
 SWEEP_TRAFFIC_SOURCES = ("paper_1407_7105_amd/csrc/cc_kernels.hip", "paper_1407_7105_amd/csrc/cc_device.h",
                          "paper_1407_7105_amd/csrc/cc_screen64.h", "paper_1407_7105_amd/csrc/cc_screen32.h",
                          "paper_1407_7105_amd/csrc/cc_tiles.h", "paper_1407_7105_amd/csrc/cc_kepler.h")
-SWEEP_TRAFFIC_SHA1 = "3066b5288128423d18c6fda405403ad301f21c94"
+SWEEP_TRAFFIC_SHA1 = "0964edf120be72f801a653ea9a3e36097f8512de"
 
 
 def sources_sha1():
