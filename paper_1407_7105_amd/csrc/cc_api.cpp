@@ -690,7 +690,6 @@ int dispatch_sets(cc_ctx *c, int k, Level &lv, double H, const std::vector<Seg> 
     // launch is not needed before this level's kick, after the whole child
     // recursion.
     hipStream_t sd = c->side[k % kSide];
-    RC(order_streams(c, c->st, sd));
     auto &d = c->deferred;
     d.on = true;
     d.k = k;
